@@ -1,0 +1,223 @@
+/*
+ * mknn.h -- repeated k-NN queries over massive sets of moving 2D objects,
+ * on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Lettich, Orlando, Silvestri, "Manycore processing of repeated k-NN
+ * queries over massive moving objects observations" (arXiv 1412.6170).
+ *
+ * Time is split into ticks (Sec. 2.2).  Per tick the caller hands over the
+ * latest position of every object (the snapshot P of the tick) and the
+ * queries Q issued during it; the library returns, for every query, its
+ * k nearest objects (Definition 1, Sec. 2.1) -- the "iterated batch
+ * processing" problem of Sec. 2.3.  Per tick it rebuilds a point-region
+ * quadtree over the snapshot (Sec. 4.1: Morton codes, radix sort, split of
+ * every quadrant holding more than the leaf capacity) and answers the
+ * queries in batched leaf sweeps that widen from each query's own leaf to
+ * the neighbouring leaves in Morton order until no leaf can still hold a
+ * nearer object (Sec. 4.2).
+ *
+ * Result contract (exact and unique):
+ *   - A query is issued by an object s and is centred on s's position; s is
+ *     excluded from its own result (by id: other objects at the same
+ *     position are kept, at distance 0).
+ *   - Objects are ranked by the squared fp32 distance
+ *         d2 = fl( fl(fl(qx-px)*fl(qx-px)) + fl(fl(qy-py)*fl(qy-py)) )
+ *     (IEEE binary32, round to nearest even, no fused multiply-add,
+ *     denormals kept), ties broken by ascending object id.  Definition 1
+ *     lets ties be broken arbitrarily; this choice makes the answer unique.
+ *   - A row holds the first min(k, n-1) objects of that order, ascending,
+ *     each with its d2; remaining slots hold id -1 and d2 +inf.  d2 is the
+ *     SQUARED distance (no square root is taken).
+ *
+ * Coordinates must be finite and lie in [0,1) (the unit square; -0.0 counts
+ * as 0).  Object ids are the positions 0..n-1 in the arrays passed to
+ * mknn_load_positions.
+ *
+ * Conventions: every call returns MKNN_OK (0) or a negative MKNN_E_* code;
+ * mknn_last_error gives the message.  No C++ exception crosses this
+ * interface.  A context is not thread-safe; separate contexts are
+ * independent.  Pointers marked "device" are HIP device (or managed)
+ * pointers on the context's device; "host" pointers are ordinary host
+ * memory.  Work is enqueued on the context's stream and the calls return
+ * before the GPU finishes, except where a call says it synchronises.
+ */
+#ifndef MKNN_H
+#define MKNN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Exported entry points (the library is built with hidden visibility). */
+#if defined(__GNUC__) || defined(__clang__)
+#define MKNN_API __attribute__((visibility("default")))
+#else
+#define MKNN_API
+#endif
+
+/* Status codes. */
+#define MKNN_OK 0
+#define MKNN_E_INVAL (-1)    /* NULL pointer, bad `where`, k < 1 or k > k_max, ... */
+#define MKNN_E_RANGE (-2)    /* a coordinate is not finite or lies outside [0,1) */
+#define MKNN_E_STATE (-3)    /* call out of order (e.g. query before advance_tick) */
+#define MKNN_E_CAPACITY (-4) /* n > n_max, nq > q_max or result entries too many */
+#define MKNN_E_NOMEM (-5)    /* device or host allocation failed */
+#define MKNN_E_DEVICE (-6)   /* a HIP error; sticky: the context must be destroyed */
+
+/* Where a buffer lives. */
+#define MKNN_HOST 0
+#define MKNN_DEVICE 1
+
+/* Largest k any query may ask for. */
+#define MKNN_K_LIMIT 128
+
+/* mknn_config.flags */
+#define MKNN_FLAG_TIMING 1 /* record per-phase device times (mknn_stats) */
+
+typedef struct mknn_ctx mknn_ctx;
+
+typedef struct mknn_config {
+    int32_t device;        /* HIP device ordinal */
+    int32_t leaf_capacity; /* th (th_quad, Sec. 4.1): a quadrant holding more
+                              than th objects is split; 0 = automatic */
+    int32_t max_level;     /* l_max (Sec. 4.1): deepest quadtree level, 1..16;
+                              0 = 16.  Leaves at this level may exceed th. */
+    int32_t k_max;         /* largest k of any query, 1..MKNN_K_LIMIT */
+    int64_t n_max;         /* capacity in objects (< 2^31) */
+    int64_t q_max;         /* capacity in queries per tick (< 2^31) */
+    void *stream;          /* hipStream_t to enqueue on (borrowed, not owned);
+                              NULL = a stream the context creates and owns */
+    int32_t k_hint;        /* typical k, used by the automatic leaf capacity;
+                              0 = k_max */
+    int32_t flags;         /* MKNN_FLAG_* */
+} mknn_config;
+
+/* Counters and device times of the last advance_tick / query. */
+typedef struct mknn_stats {
+    int64_t tick;          /* ticks advanced since the last load */
+    int64_t n;             /* objects in the snapshot */
+    int64_t nq;            /* queries of the last mknn_query */
+    int64_t leaves;        /* non-empty quadtree leaves (active cells, Sec. 4.1) */
+    int64_t nodes;         /* quadtree nodes kept (inner + non-empty leaves) */
+    int32_t leaf_capacity; /* th used for the current index */
+    int32_t deepest_level; /* l_deep: deepest leaf level (Sec. 4.1) */
+    float ms_build;        /* device time of the index build (MKNN_FLAG_TIMING) */
+    float ms_query;        /* device time of the query, all kernels */
+    float ms_query_main;   /* device time of the leaf-sweep kernel alone */
+    float reserved[5];
+} mknn_stats;
+
+/*
+ * mknn_create -- allocate a context and all its device memory, sized by
+ * cfg->n_max, cfg->q_max and cfg->k_max.  *out receives the context.
+ * Errors: MKNN_E_INVAL (NULL, capacities out of range), MKNN_E_NOMEM,
+ * MKNN_E_DEVICE (bad device).  On error *out is set to NULL.
+ */
+MKNN_API int mknn_create(const mknn_config *cfg, mknn_ctx **out);
+
+/* mknn_destroy -- wait for the context's work and free everything.  NULL is
+ * allowed.  A borrowed stream is left alone. */
+MKNN_API int mknn_destroy(mknn_ctx *ctx);
+
+/*
+ * mknn_load_positions -- replace the snapshot with n objects (Sec. 2.2:
+ * only the latest update of each object counts).  x[i], y[i] is object i's
+ * position, two arrays of n floats, host or device memory per `where`.
+ * The data is copied; host arrays may be reused when the call returns,
+ * device arrays once the context's stream has reached the copy.
+ * Host input is validated during the call (MKNN_E_RANGE leaves the previous
+ * snapshot in place).  Device input is validated on the device; a bad value
+ * makes the next mknn_sync / mknn_fetch return MKNN_E_RANGE.
+ * Errors: MKNN_E_INVAL, MKNN_E_CAPACITY (n > n_max), MKNN_E_RANGE.
+ * After a load, mknn_advance_tick must run before the next query.
+ */
+MKNN_API int mknn_load_positions(mknn_ctx *ctx, const float *x, const float *y, int64_t n,
+                        int32_t where);
+
+/*
+ * mknn_advance_tick -- enqueue the index build over the current snapshot
+ * (Sec. 4.1: Morton codes at level 16, radix sort of (code, id), split of
+ * every quadrant holding more than the leaf capacity up to max_level, leaf
+ * and node tables).  Asynchronous.  Errors: MKNN_E_STATE (nothing loaded).
+ */
+MKNN_API int mknn_advance_tick(mknn_ctx *ctx);
+
+/*
+ * mknn_query -- enqueue one k-NN query per entry (Sec. 4.2).  Query i is
+ * issued by object issuers[i] (NULL = every object 0..n-1, in order, and
+ * then nq must equal n), centred on its position and excluding it, and asks
+ * for ks[i] results (NULL = k_uniform for all).  Every k must be in
+ * [1, k_max].  issuers and ks are int32 arrays of nq entries in host or
+ * device memory per `where`; they are read before the call returns (host)
+ * or once the stream reaches the query (device).  Results stay on the device,
+ * owned by the context, until the next mknn_query.
+ * Errors: MKNN_E_INVAL (bad issuer or k, host-side), MKNN_E_STATE (no tick
+ * since the last load), MKNN_E_CAPACITY (nq > q_max or, for variable k, the
+ * sum of ks above q_max * k_max).
+ */
+MKNN_API int mknn_query(mknn_ctx *ctx, const int32_t *issuers, const int32_t *ks, int64_t nq,
+               int32_t k_uniform, int32_t where);
+
+/*
+ * mknn_fetch -- synchronise, then copy the last query's results into
+ * caller-owned buffers (host or device per `where`).  Rows are in query
+ * order.  Uniform k: ids and d2 are dense row-major [nq][k]; offsets may be
+ * NULL.  Variable k: row i occupies entries offsets[i] .. offsets[i+1]-1
+ * (offsets has nq+1 int64 entries, offsets[i+1]-offsets[i] = ks[i]).
+ * counts[i] = min(k_i, n-1).  Any of ids, d2, counts, offsets may be NULL
+ * to skip it.  Sizes: see mknn_result_size.
+ * Errors: MKNN_E_STATE (no query yet), MKNN_E_RANGE (bad device input),
+ * MKNN_E_DEVICE.
+ */
+MKNN_API int mknn_fetch(mknn_ctx *ctx, int32_t *ids, float *d2, int32_t *counts, int64_t *offsets,
+               int32_t where);
+
+/* mknn_result_size -- number of queries and of result entries (row slots)
+ * of the last query. */
+MKNN_API int mknn_result_size(const mknn_ctx *ctx, int64_t *nq, int64_t *entries);
+
+/*
+ * mknn_result_device -- device pointers to the last query's results inside
+ * the context (valid until the next mknn_query or mknn_destroy; do not
+ * free).  Same layout as mknn_fetch.  offsets is NULL for uniform k.  The
+ * results are complete once the context's stream has passed the query.
+ */
+MKNN_API int mknn_result_device(const mknn_ctx *ctx, const int32_t **ids, const float **d2,
+                       const int32_t **counts, const int64_t **offsets);
+
+/*
+ * mknn_index_fetch -- synchronise and copy the current index to host
+ * buffers, for inspection and tests.  Objects: codes[n] (level-16 Morton
+ * codes in sorted order) and ids[n] (object id at each sorted position).
+ * Leaves, in Morton order: level[L], prefix[L] (quadrant id at its level),
+ * begin[L], end[L] (half-open range of sorted positions); leaf_cap is the
+ * room in the leaf arrays, *n_leaves receives the leaf count (the call
+ * returns MKNN_E_CAPACITY if it exceeds leaf_cap).  Any array may be NULL.
+ */
+MKNN_API int mknn_index_fetch(mknn_ctx *ctx, uint32_t *codes, int32_t *ids, int32_t *level,
+                     uint32_t *prefix, int64_t *begin, int64_t *end, int64_t leaf_cap,
+                     int64_t *n_leaves);
+
+/* mknn_sync -- wait for all enqueued work; reports deferred errors. */
+MKNN_API int mknn_sync(mknn_ctx *ctx);
+
+/* mknn_get_stats -- counters of the current index and last query; device
+ * times need MKNN_FLAG_TIMING and a prior mknn_sync. */
+MKNN_API int mknn_get_stats(const mknn_ctx *ctx, mknn_stats *out);
+
+/* mknn_last_error -- message of the context's last error ("" if none). */
+MKNN_API const char *mknn_last_error(const mknn_ctx *ctx);
+
+/* mknn_status_str -- name of a status code. */
+MKNN_API const char *mknn_status_str(int status);
+
+/* mknn_default_leaf_capacity -- the automatic leaf capacity for a given k. */
+MKNN_API int32_t mknn_default_leaf_capacity(int32_t k);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MKNN_H */

@@ -1,0 +1,264 @@
+"""ctypes binding of libmknn.so (the C ABI in include/mknn.h).
+
+Argument marshalling only: every step of the tick runs in the HIP library.
+Host arrays are numpy; device arrays are torch tensors on the context's
+device (torch only provides device memory and streams).  A missing library
+raises immediately -- there is no CPU fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmknn.so")
+
+MKNN_OK = 0
+MKNN_HOST = 0
+MKNN_DEVICE = 1
+MKNN_FLAG_TIMING = 1
+MKNN_K_LIMIT = 128
+STATUS = {0: "MKNN_OK", -1: "MKNN_E_INVAL", -2: "MKNN_E_RANGE", -3: "MKNN_E_STATE",
+          -4: "MKNN_E_CAPACITY", -5: "MKNN_E_NOMEM", -6: "MKNN_E_DEVICE"}
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("leaf_capacity", ctypes.c_int32),
+                ("max_level", ctypes.c_int32), ("k_max", ctypes.c_int32),
+                ("n_max", ctypes.c_int64), ("q_max", ctypes.c_int64),
+                ("stream", ctypes.c_void_p), ("k_hint", ctypes.c_int32),
+                ("flags", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("tick", ctypes.c_int64), ("n", ctypes.c_int64), ("nq", ctypes.c_int64),
+                ("leaves", ctypes.c_int64), ("nodes", ctypes.c_int64),
+                ("leaf_capacity", ctypes.c_int32), ("deepest_level", ctypes.c_int32),
+                ("ms_build", ctypes.c_float), ("ms_query", ctypes.c_float),
+                ("ms_query_main", ctypes.c_float), ("reserved", ctypes.c_float * 5)]
+
+
+class MknnError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (STATUS.get(code, "?"), code, msg))
+        self.code = code
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+
+
+def lib():
+    """Load libmknn.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libmknn.so is not built (run `python -m paper_1412_6170_amd.build`"
+                              " or __graft_entry__.build()); there is no CPU fallback")
+        L = ctypes.CDLL(LIB_PATH)
+        sig = {
+            "mknn_create": ([ctypes.POINTER(Config), ctypes.POINTER(_vp)], _i32),
+            "mknn_destroy": ([_vp], _i32),
+            "mknn_load_positions": ([_vp, _vp, _vp, _i64, _i32], _i32),
+            "mknn_advance_tick": ([_vp], _i32),
+            "mknn_query": ([_vp, _vp, _vp, _i64, _i32, _i32], _i32),
+            "mknn_fetch": ([_vp, _vp, _vp, _vp, _vp, _i32], _i32),
+            "mknn_result_size": ([_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64)], _i32),
+            "mknn_result_device": ([_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                    ctypes.POINTER(_vp), ctypes.POINTER(_vp)], _i32),
+            "mknn_index_fetch": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64,
+                                  ctypes.POINTER(_i64)], _i32),
+            "mknn_sync": ([_vp], _i32),
+            "mknn_get_stats": ([_vp, ctypes.POINTER(Stats)], _i32),
+            "mknn_last_error": ([_vp], ctypes.c_char_p),
+            "mknn_status_str": ([_i32], ctypes.c_char_p),
+            "mknn_default_leaf_capacity": ([_i32], _i32),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def default_leaf_capacity(k):
+    return int(lib().mknn_default_leaf_capacity(int(k)))
+
+
+def _is_tensor(a):
+    return type(a).__module__.startswith("torch")
+
+
+def _host_ptr(a, dtype):
+    return a.ctypes.data_as(_vp) if a is not None else None
+
+
+class Context:
+    """One mknn context: device memory for n_max objects and q_max queries
+    of up to k_max neighbours each."""
+
+    def __init__(self, n_max, q_max=None, k_max=32, leaf_capacity=0, max_level=0, k_hint=0,
+                 device=0, stream=None, timing=False):
+        cfg = Config()
+        cfg.device = device
+        cfg.leaf_capacity = int(leaf_capacity)
+        cfg.max_level = int(max_level)
+        cfg.k_max = int(k_max)
+        cfg.n_max = int(n_max)
+        cfg.q_max = int(q_max if q_max is not None else n_max)
+        cfg.stream = stream
+        cfg.k_hint = int(k_hint)
+        cfg.flags = MKNN_FLAG_TIMING if timing else 0
+        self.cfg = cfg
+        h = _vp()
+        rc = lib().mknn_create(ctypes.byref(cfg), ctypes.byref(h))
+        if rc != 0:
+            raise MknnError(rc, "mknn_create failed")
+        self._h = h
+        self._keep = []
+
+    # -- plumbing ------------------------------------------------------------
+    def _check(self, rc):
+        if rc != 0:
+            raise MknnError(rc, lib().mknn_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().mknn_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _arg(a, dtype):
+        """(pointer, where, keepalive) for a host numpy array or a device
+        torch tensor."""
+        if a is None:
+            return None, None, None
+        if _is_tensor(a):
+            if not a.is_cuda:
+                a = a.numpy()
+            else:
+                import torch
+                tdt = {np.float32: torch.float32, np.int32: torch.int32}[dtype]
+                if a.dtype != tdt or not a.is_contiguous():
+                    raise TypeError("device arrays must be contiguous %s" % tdt)
+                return ctypes.c_void_p(a.data_ptr()), MKNN_DEVICE, a
+        a = np.ascontiguousarray(a, dtype=dtype)
+        return a.ctypes.data_as(_vp), MKNN_HOST, a
+
+    # -- the four verbs ------------------------------------------------------
+    def load_positions(self, x, y):
+        px, wx, kx = self._arg(x, np.float32)
+        py, wy, ky = self._arg(y, np.float32)
+        if wx != wy:
+            raise TypeError("x and y must both be host or both be device arrays")
+        n = len(kx)
+        if len(ky) != n:
+            raise ValueError("x and y differ in length")
+        self._check(lib().mknn_load_positions(self._h, px, py, n, wx))
+        self._keep = [kx, ky]
+
+    def advance_tick(self):
+        self._check(lib().mknn_advance_tick(self._h))
+
+    def query(self, k=None, issuers=None, ks=None, nq=None):
+        pi, wi, ki = self._arg(issuers, np.int32)
+        pk, wk, kk = self._arg(ks, np.int32)
+        where = wi if wi is not None else (wk if wk is not None else MKNN_HOST)
+        if wi is not None and wk is not None and wi != wk:
+            raise TypeError("issuers and ks must live in the same place")
+        if nq is None:
+            if ki is not None:
+                nq = len(ki)
+            elif kk is not None:
+                nq = len(kk)
+            else:
+                nq = self.stats()["n"]
+        self._check(lib().mknn_query(self._h, pi, pk, int(nq), int(k or 0), where))
+        self._qkeep = [ki, kk]
+        self._last_k = None if ks is not None else int(k)
+
+    def result_size(self):
+        nq, ne = _i64(), _i64()
+        self._check(lib().mknn_result_size(self._h, ctypes.byref(nq), ctypes.byref(ne)))
+        return nq.value, ne.value
+
+    def fetch(self):
+        """Host copies: (ids, d2, counts, offsets).  Uniform k gives [nq, k]
+        arrays and offsets None; variable k gives flat arrays and offsets."""
+        nq, ne = self.result_size()
+        ids = np.empty(max(ne, 1), np.int32)
+        d2 = np.empty(max(ne, 1), np.float32)
+        cnt = np.empty(max(nq, 1), np.int32)
+        off = np.empty(nq + 1, np.int64)
+        self._check(lib().mknn_fetch(self._h, ids.ctypes.data_as(_vp), d2.ctypes.data_as(_vp),
+                                     cnt.ctypes.data_as(_vp), off.ctypes.data_as(_vp),
+                                     MKNN_HOST))
+        ids, d2, cnt = ids[:ne], d2[:ne], cnt[:nq]
+        if self._last_k is not None:
+            k = self._last_k
+            return ids.reshape(nq, k), d2.reshape(nq, k), cnt, None
+        return ids, d2, cnt, off
+
+    def result_device_ptrs(self):
+        ids, d2, cnt, off = _vp(), _vp(), _vp(), _vp()
+        self._check(lib().mknn_result_device(self._h, ctypes.byref(ids), ctypes.byref(d2),
+                                             ctypes.byref(cnt), ctypes.byref(off)))
+        return ids.value, d2.value, cnt.value, off.value
+
+    def sync(self):
+        self._check(lib().mknn_sync(self._h))
+
+    def stats(self):
+        s = Stats()
+        self._check(lib().mknn_get_stats(self._h, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in Stats._fields_ if f != "reserved"}
+
+    def index(self):
+        """The current index as host arrays (same keys as the oracle's
+        build_index, without n_empty_leaves)."""
+        st = self.stats()
+        n = st["n"]
+        cap = max(int(st["leaves"]), 1)
+        codes = np.empty(max(n, 1), np.uint32)
+        ids = np.empty(max(n, 1), np.int32)
+        lev = np.empty(cap, np.int32)
+        pre = np.empty(cap, np.uint32)
+        beg = np.empty(cap, np.int64)
+        end = np.empty(cap, np.int64)
+        nl = _i64()
+        self._check(lib().mknn_index_fetch(
+            self._h, codes.ctypes.data_as(_vp), ids.ctypes.data_as(_vp),
+            lev.ctypes.data_as(_vp), pre.ctypes.data_as(_vp), beg.ctypes.data_as(_vp),
+            end.ctypes.data_as(_vp), cap, ctypes.byref(nl)))
+        m = nl.value
+        return {"codes": codes[:n], "ids": ids[:n], "leaf_level": lev[:m], "leaf_prefix": pre[:m],
+                "leaf_begin": beg[:m], "leaf_end": end[:m], "nodes": st["nodes"]}
+
+
+def knn_tick(x, y, k=None, issuers=None, ks=None, leaf_capacity=0, max_level=0, k_max=None):
+    """One tick through a fresh context: load, advance, query, fetch."""
+    n = len(x)
+    nq = n if issuers is None else len(issuers)
+    if k_max is None:
+        k_max = int(k) if ks is None else int(np.max(ks)) if len(ks) else 1
+    with Context(max(n, 1), max(nq, 1), k_max, leaf_capacity=leaf_capacity,
+                 max_level=max_level) as c:
+        c.load_positions(x, y)
+        c.advance_tick()
+        c.query(k=k, issuers=issuers, ks=ks, nq=nq)
+        return c.fetch()

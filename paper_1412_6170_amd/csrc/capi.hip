@@ -1,0 +1,586 @@
+// C ABI of the mknn library: contexts, device memory, argument checks and
+// the enqueueing of the index build and the query kernels.  Declarations
+// and the contract of every entry point are in include/mknn.h.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <vector>
+
+#include "mknn.h"
+#include "mknn_internal.hpp"
+#include "query.hpp"
+
+using namespace mknn;
+
+struct mknn_ctx {
+    mknn_config cfg{};
+    int th = 0, L = 16, k_max = 1;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    bool dead = false;         // sticky device error
+    std::string err;
+
+    bool loaded = false, ticked = false, queried = false;
+    int64_t n = 0, nq = 0, entries = 0;
+    int32_t k_uniform = 0;
+    bool var_k = false;
+    int64_t ticks = 0;
+
+    float *x = nullptr, *y = nullptr;
+    IndexBuffers ix{};
+    SortBuffers qs{};          // query-order sort (subset queries)
+    int32_t *issuers = nullptr, *ks = nullptr;  // staging of host query arrays
+    uint32_t *kcount = nullptr, *kscan = nullptr, *ktotal = nullptr;
+    int64_t *offsets = nullptr;
+    int32_t *out_ids = nullptr;
+    float *out_d2 = nullptr;
+    int32_t *out_cnt = nullptr;
+
+    hipEvent_t ev[6]{};
+    bool have_events = false;
+    std::vector<void *> allocs;
+};
+
+namespace {
+
+int fail(mknn_ctx *c, int code, const char *fmt, const char *detail = "")
+{
+    if (c) {
+        char buf[512];
+        snprintf(buf, sizeof buf, fmt, detail);
+        c->err = buf;
+        if (code == MKNN_E_DEVICE) c->dead = true;
+    }
+    return code;
+}
+
+int hip_fail(mknn_ctx *c, hipError_t e, const char *where)
+{
+    char buf[512];
+    snprintf(buf, sizeof buf, "%s: %s", where, hipGetErrorString(e));
+    return fail(c, MKNN_E_DEVICE, "%s", buf);
+}
+
+#define HIP_OR_FAIL(ctx, call)                                   \
+    do {                                                         \
+        hipError_t e_ = (call);                                  \
+        if (e_ != hipSuccess) return hip_fail((ctx), e_, #call); \
+    } while (0)
+
+template <typename T>
+int dalloc(mknn_ctx *c, T **p, int64_t count)
+{
+    if (count < 1) count = 1;
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, (size_t)count * sizeof(T));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, MKNN_E_NOMEM, "device allocation of %s failed",
+                    std::to_string((size_t)count * sizeof(T)).c_str());
+    }
+    c->allocs.push_back(q);
+    *p = (T *)q;
+    return MKNN_OK;
+}
+
+int check_launch(mknn_ctx *c, const char *what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(c, e, what);
+    return MKNN_OK;
+}
+
+int bits_for(int64_t n)
+{
+    int b = 1;
+    while (b < 32 && ((int64_t)1 << b) < n) ++b;
+    return ((b + kRadixBits - 1) / kRadixBits) * kRadixBits;
+}
+
+__global__ void k_reset_counters(IndexCounters *ctr) { *ctr = IndexCounters{}; }
+
+int read_counters(mknn_ctx *c, IndexCounters *h)
+{
+    HIP_OR_FAIL(c, hipMemcpyAsync(h, c->ix.ctr, sizeof *h, hipMemcpyDeviceToHost, c->stream));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    return MKNN_OK;
+}
+
+int check_deferred(mknn_ctx *c)
+{
+    if (!c->ticked) return MKNN_OK;
+    IndexCounters h{};
+    int rc = read_counters(c, &h);
+    if (rc) return rc;
+    if (h.bad_input & 1u)
+        return fail(c, MKNN_E_RANGE, "a device coordinate is not finite or outside [0,1)%s");
+    if (h.bad_input & 2u) return fail(c, MKNN_E_INVAL, "a device issuer is outside [0,n)%s");
+    if (h.bad_input & 4u) return fail(c, MKNN_E_INVAL, "a device k is outside [1,k_max]%s");
+    if (h.bad_input & 8u) return fail(c, MKNN_E_DEVICE, "node table capacity exceeded%s");
+    return MKNN_OK;
+}
+
+bool valid_where(int32_t w) { return w == MKNN_HOST || w == MKNN_DEVICE; }
+
+}  // namespace
+
+extern "C" {
+
+const char *mknn_status_str(int s)
+{
+    switch (s) {
+    case MKNN_OK: return "MKNN_OK";
+    case MKNN_E_INVAL: return "MKNN_E_INVAL";
+    case MKNN_E_RANGE: return "MKNN_E_RANGE";
+    case MKNN_E_STATE: return "MKNN_E_STATE";
+    case MKNN_E_CAPACITY: return "MKNN_E_CAPACITY";
+    case MKNN_E_NOMEM: return "MKNN_E_NOMEM";
+    case MKNN_E_DEVICE: return "MKNN_E_DEVICE";
+    default: return "MKNN_E_UNKNOWN";
+    }
+}
+
+int32_t mknn_default_leaf_capacity(int32_t k)
+{
+    // Paper's setting (Sec. 6): 192 for k < 32, 12k for 32..128, 2048 above.
+    if (k < 32) return 192;
+    if (k <= 128) return 12 * k;
+    return 2048;
+}
+
+const char *mknn_last_error(const mknn_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+int mknn_destroy(mknn_ctx *c)
+{
+    if (!c) return MKNN_OK;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipSetDevice(c->cfg.device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (void *p : c->allocs) (void)hipFree(p);
+    if (c->have_events)
+        for (auto &e : c->ev) (void)hipEventDestroy(e);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    (void)hipSetDevice(dev);
+    delete c;
+    return MKNN_OK;
+}
+
+int mknn_create(const mknn_config *cfg, mknn_ctx **out)
+{
+    if (!out) return MKNN_E_INVAL;
+    *out = nullptr;
+    if (!cfg) return MKNN_E_INVAL;
+    if (cfg->n_max < 1 || cfg->n_max >= ((int64_t)1 << 31) || cfg->q_max < 1 ||
+        cfg->q_max >= ((int64_t)1 << 31) || cfg->k_max < 1 || cfg->k_max > MKNN_K_LIMIT ||
+        cfg->max_level < 0 || cfg->max_level > kCodeLevels || cfg->leaf_capacity < 0 ||
+        cfg->k_hint < 0 || cfg->k_hint > MKNN_K_LIMIT)
+        return MKNN_E_INVAL;
+    if ((double)cfg->q_max * cfg->k_max >= 4294967295.0) return MKNN_E_CAPACITY;
+
+    mknn_ctx *c = new (std::nothrow) mknn_ctx;
+    if (!c) return MKNN_E_NOMEM;
+    c->cfg = *cfg;
+    c->L = cfg->max_level ? cfg->max_level : kCodeLevels;
+    c->k_max = cfg->k_max;
+    const int kh = cfg->k_hint ? cfg->k_hint : cfg->k_max;
+    c->th = cfg->leaf_capacity ? cfg->leaf_capacity : mknn_default_leaf_capacity(kh);
+
+    hipError_t e = hipSetDevice(cfg->device);
+    if (e != hipSuccess) {
+        delete c;
+        return MKNN_E_DEVICE;
+    }
+    int rc = MKNN_OK;
+    if (cfg->stream) {
+        c->stream = (hipStream_t)cfg->stream;
+    } else {
+        e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            delete c;
+            return MKNN_E_DEVICE;
+        }
+        c->own_stream = true;
+    }
+    const int64_t N = cfg->n_max, Q = cfg->q_max;
+    const int64_t NQ = N > Q ? N : Q;
+    const int64_t node_cap = node_capacity(N, c->th, c->L);
+    const int64_t hist = radix_hist_elems(NQ);
+    int64_t stmp = scan_tmp_elems(hist);
+    if (scan_tmp_elems(NQ + 1) > stmp) stmp = scan_tmp_elems(NQ + 1);
+    c->ix.n_cap = N;
+    c->ix.node_cap = node_cap;
+    c->ix.hist_cap = hist;
+    c->ix.scan_tmp_cap = stmp;
+#define A(p, cnt)                       \
+    if (!rc) rc = dalloc(c, &(p), (cnt));
+    A(c->x, N);
+    A(c->y, N);
+    A(c->ix.sort.keys[0], N);
+    A(c->ix.sort.keys[1], N);
+    A(c->ix.sort.vals[0], N);
+    A(c->ix.sort.vals[1], N);
+    A(c->ix.sort.hist, hist);
+    A(c->ix.sort.scan_tmp, stmp);
+    A(c->ix.pts, N);
+    A(c->ix.inv, N);
+    A(c->ix.leaf_of, N);
+    A(c->ix.flags, N);
+    A(c->ix.leaf_begin, N);
+    A(c->ix.leaf_end, N);
+    A(c->ix.leaf_level, N);
+    A(c->ix.cnt_f, N);
+    A(c->ix.cnt_r, N);
+    A(c->ix.leaf_node_f, N);
+    A(c->ix.leaf_node_r, N);
+    A(c->ix.fwd, node_cap);
+    A(c->ix.rev, node_cap);
+    A(c->ix.ctr, 1);
+    A(c->qs.keys[0], Q);
+    A(c->qs.keys[1], Q);
+    A(c->qs.vals[0], Q);
+    A(c->qs.vals[1], Q);
+    c->qs.hist = c->ix.sort.hist;
+    c->qs.scan_tmp = c->ix.sort.scan_tmp;
+    A(c->issuers, Q);
+    A(c->ks, Q);
+    A(c->kcount, Q);
+    A(c->kscan, Q);
+    A(c->ktotal, 1);
+    A(c->offsets, Q + 1);
+    A(c->out_ids, Q * c->k_max);
+    A(c->out_d2, Q * c->k_max);
+    A(c->out_cnt, Q);
+#undef A
+    if (!rc) {
+        c->have_events = true;
+        for (auto &ev : c->ev)
+            if (hipEventCreate(&ev) != hipSuccess) c->have_events = false;
+        k_reset_counters<<<1, 1, 0, c->stream>>>(c->ix.ctr);
+        rc = check_launch(c, "reset counters");
+    }
+    if (rc) {
+        mknn_destroy(c);
+        return rc;
+    }
+    *out = c;
+    return MKNN_OK;
+}
+
+int mknn_load_positions(mknn_ctx *c, const float *x, const float *y, int64_t n, int32_t where)
+{
+    if (!c) return MKNN_E_INVAL;
+    if (c->dead) return fail(c, MKNN_E_DEVICE, "context has a sticky device error%s");
+    if (!valid_where(where)) return fail(c, MKNN_E_INVAL, "bad `where`%s");
+    if (n < 0 || (n > 0 && (!x || !y))) return fail(c, MKNN_E_INVAL, "bad positions%s");
+    if (n > c->cfg.n_max) return fail(c, MKNN_E_CAPACITY, "n exceeds n_max%s");
+    if (where == MKNN_HOST) {
+        for (int64_t i = 0; i < n; ++i) {
+            const float a = x[i], b = y[i];
+            if (!(a >= 0.0f && a < 1.0f && b >= 0.0f && b < 1.0f))
+                return fail(c, MKNN_E_RANGE, "object %s: coordinate not finite or outside [0,1)",
+                            std::to_string(i).c_str());
+        }
+    }
+    HIP_OR_FAIL(c, hipSetDevice(c->cfg.device));
+    const hipMemcpyKind kind = where == MKNN_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    if (n > 0) {
+        HIP_OR_FAIL(c, hipMemcpyAsync(c->x, x, (size_t)n * sizeof(float), kind, c->stream));
+        HIP_OR_FAIL(c, hipMemcpyAsync(c->y, y, (size_t)n * sizeof(float), kind, c->stream));
+        if (where == MKNN_HOST) HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    }
+    c->n = n;
+    c->loaded = true;
+    c->ticked = false;
+    c->queried = false;
+    c->ticks = 0;
+    return MKNN_OK;
+}
+
+int mknn_advance_tick(mknn_ctx *c)
+{
+    if (!c) return MKNN_E_INVAL;
+    if (c->dead) return fail(c, MKNN_E_DEVICE, "context has a sticky device error%s");
+    if (!c->loaded) return fail(c, MKNN_E_STATE, "advance_tick before load_positions%s");
+    HIP_OR_FAIL(c, hipSetDevice(c->cfg.device));
+    const bool timing = (c->cfg.flags & MKNN_FLAG_TIMING) && c->have_events;
+    if (timing) HIP_OR_FAIL(c, hipEventRecord(c->ev[0], c->stream));
+    k_reset_counters<<<1, 1, 0, c->stream>>>(c->ix.ctr);
+    launch_build_index(c->ix, c->x, c->y, c->n, c->th, c->L, c->stream);
+    int rc = check_launch(c, "index build");
+    if (rc) return rc;
+    if (timing) HIP_OR_FAIL(c, hipEventRecord(c->ev[1], c->stream));
+    c->ticked = true;
+    c->queried = false;
+    ++c->ticks;
+    return MKNN_OK;
+}
+
+int mknn_query(mknn_ctx *c, const int32_t *issuers, const int32_t *ks, int64_t nq,
+               int32_t k_uniform, int32_t where)
+{
+    if (!c) return MKNN_E_INVAL;
+    if (c->dead) return fail(c, MKNN_E_DEVICE, "context has a sticky device error%s");
+    if (!valid_where(where)) return fail(c, MKNN_E_INVAL, "bad `where`%s");
+    if (!c->ticked) return fail(c, MKNN_E_STATE, "query before advance_tick%s");
+    if (nq < 0) return fail(c, MKNN_E_INVAL, "nq < 0%s");
+    if (nq > c->cfg.q_max) return fail(c, MKNN_E_CAPACITY, "nq exceeds q_max%s");
+    if (!issuers && nq != c->n)
+        return fail(c, MKNN_E_INVAL, "issuers NULL requires nq == n%s");
+    if (c->n == 0 && nq > 0) return fail(c, MKNN_E_INVAL, "queries need at least one object%s");
+    if (!ks && (k_uniform < 1 || k_uniform > c->k_max))
+        return fail(c, MKNN_E_INVAL, "k outside [1, k_max]%s");
+    int kmax_call = ks ? c->k_max : k_uniform;
+    if (where == MKNN_HOST) {
+        int kmx = 1;
+        for (int64_t i = 0; i < nq; ++i) {
+            if (issuers && (issuers[i] < 0 || issuers[i] >= c->n))
+                return fail(c, MKNN_E_INVAL, "issuer %s outside [0,n)",
+                            std::to_string(i).c_str());
+            if (ks) {
+                if (ks[i] < 1 || ks[i] > c->k_max)
+                    return fail(c, MKNN_E_INVAL, "k of query %s outside [1,k_max]",
+                                std::to_string(i).c_str());
+                if (ks[i] > kmx) kmx = ks[i];
+            }
+        }
+        if (ks) kmax_call = kmx;
+    }
+    HIP_OR_FAIL(c, hipSetDevice(c->cfg.device));
+    const bool timing = (c->cfg.flags & MKNN_FLAG_TIMING) && c->have_events;
+    if (timing) HIP_OR_FAIL(c, hipEventRecord(c->ev[2], c->stream));
+
+    const int32_t *d_iss = issuers, *d_ks = ks;
+    if (where == MKNN_HOST && nq > 0) {
+        if (issuers) {
+            HIP_OR_FAIL(c, hipMemcpyAsync(c->issuers, issuers, (size_t)nq * 4,
+                                          hipMemcpyHostToDevice, c->stream));
+            d_iss = c->issuers;
+        }
+        if (ks) {
+            HIP_OR_FAIL(c, hipMemcpyAsync(c->ks, ks, (size_t)nq * 4, hipMemcpyHostToDevice,
+                                          c->stream));
+            d_ks = c->ks;
+        }
+    }
+
+    QueryArgs qa{};
+    qa.pts = c->ix.pts;
+    qa.n = (uint32_t)c->n;
+    qa.fwd = c->ix.fwd;
+    qa.rev = c->ix.rev;
+    qa.leaf_of = c->ix.leaf_of;
+    qa.leaf_begin = c->ix.leaf_begin;
+    qa.leaf_end = c->ix.leaf_end;
+    qa.leaf_node_f = c->ix.leaf_node_f;
+    qa.leaf_node_r = c->ix.leaf_node_r;
+    qa.ctr = c->ix.ctr;
+    qa.node_cap = (int32_t)c->ix.node_cap;
+    qa.nq = (uint32_t)nq;
+    qa.k_uniform = ks ? 0 : k_uniform;
+    qa.out_ids = c->out_ids;
+    qa.out_d2 = c->out_d2;
+    qa.out_cnt = c->out_cnt;
+
+    if ((d_iss || d_ks) && nq > 0) {
+        QueryPrep p{};
+        p.issuers = d_iss;
+        p.ks = d_ks;
+        p.nq = (uint32_t)nq;
+        p.n = (uint32_t)c->n;
+        p.k_max = c->k_max;
+        p.inv = c->ix.inv;
+        p.sort = c->qs;
+        p.kcount = c->kcount;
+        p.ctr = c->ix.ctr;
+        launch_query_prep(p, c->stream);
+        if (d_iss) {
+            const int res = launch_radix_sort(c->qs, nq, bits_for(c->n), c->stream);
+            qa.qpos = (const int32_t *)c->qs.keys[res];
+            qa.qrow = (const int32_t *)c->qs.vals[res];
+        }
+        if (d_ks) {
+            launch_offsets(c->kcount, (uint32_t)nq, c->kscan, c->ix.sort.scan_tmp, c->ktotal,
+                           c->offsets, c->stream);
+            qa.ks = (const int32_t *)c->kcount;
+            qa.row_off = c->offsets;
+        }
+    } else if (d_ks) {
+        // nq == 0 with variable k: a single zero offset.
+        launch_offsets(c->kcount, 0, c->kscan, c->ix.sort.scan_tmp, c->ktotal, c->offsets,
+                       c->stream);
+    }
+    if (timing) HIP_OR_FAIL(c, hipEventRecord(c->ev[4], c->stream));
+    launch_knn(qa, k_class(kmax_call), c->stream);
+    int rc = check_launch(c, "k-NN query");
+    if (rc) return rc;
+    if (timing) {
+        HIP_OR_FAIL(c, hipEventRecord(c->ev[5], c->stream));
+        HIP_OR_FAIL(c, hipEventRecord(c->ev[3], c->stream));
+    }
+    c->queried = true;
+    c->nq = nq;
+    c->var_k = ks != nullptr;
+    c->k_uniform = ks ? 0 : k_uniform;
+    if (!ks) {
+        c->entries = nq * (int64_t)k_uniform;
+    } else if (where == MKNN_HOST) {
+        int64_t s = 0;
+        for (int64_t i = 0; i < nq; ++i) s += ks[i];
+        c->entries = s;
+    } else {
+        c->entries = -1;  // known after synchronisation
+    }
+    return MKNN_OK;
+}
+
+static int resolve_entries(mknn_ctx *c)
+{
+    if (c->entries >= 0) return MKNN_OK;
+    int64_t tot = 0;
+    HIP_OR_FAIL(c, hipMemcpyAsync(&tot, c->offsets + c->nq, sizeof tot, hipMemcpyDeviceToHost,
+                                  c->stream));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    c->entries = tot;
+    return MKNN_OK;
+}
+
+int mknn_sync(mknn_ctx *c)
+{
+    if (!c) return MKNN_E_INVAL;
+    if (c->dead) return fail(c, MKNN_E_DEVICE, "context has a sticky device error%s");
+    HIP_OR_FAIL(c, hipSetDevice(c->cfg.device));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    return check_deferred(c);
+}
+
+int mknn_result_size(const mknn_ctx *cc, int64_t *nq, int64_t *entries)
+{
+    mknn_ctx *c = const_cast<mknn_ctx *>(cc);
+    if (!c) return MKNN_E_INVAL;
+    if (!c->queried) return fail(c, MKNN_E_STATE, "no query yet%s");
+    int rc = resolve_entries(c);
+    if (rc) return rc;
+    if (nq) *nq = c->nq;
+    if (entries) *entries = c->entries;
+    return MKNN_OK;
+}
+
+int mknn_result_device(const mknn_ctx *cc, const int32_t **ids, const float **d2,
+                       const int32_t **counts, const int64_t **offsets)
+{
+    mknn_ctx *c = const_cast<mknn_ctx *>(cc);
+    if (!c) return MKNN_E_INVAL;
+    if (!c->queried) return fail(c, MKNN_E_STATE, "no query yet%s");
+    if (ids) *ids = c->out_ids;
+    if (d2) *d2 = c->out_d2;
+    if (counts) *counts = c->out_cnt;
+    if (offsets) *offsets = c->var_k ? c->offsets : nullptr;
+    return MKNN_OK;
+}
+
+int mknn_fetch(mknn_ctx *c, int32_t *ids, float *d2, int32_t *counts, int64_t *offsets,
+               int32_t where)
+{
+    if (!c) return MKNN_E_INVAL;
+    if (!valid_where(where)) return fail(c, MKNN_E_INVAL, "bad `where`%s");
+    if (!c->queried) return fail(c, MKNN_E_STATE, "fetch before query%s");
+    int rc = mknn_sync(c);
+    if (rc) return rc;
+    rc = resolve_entries(c);
+    if (rc) return rc;
+    const hipMemcpyKind kind = where == MKNN_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    const size_t ne = (size_t)c->entries, nq = (size_t)c->nq;
+    if (ids && ne) HIP_OR_FAIL(c, hipMemcpyAsync(ids, c->out_ids, ne * 4, kind, c->stream));
+    if (d2 && ne) HIP_OR_FAIL(c, hipMemcpyAsync(d2, c->out_d2, ne * 4, kind, c->stream));
+    if (counts && nq) HIP_OR_FAIL(c, hipMemcpyAsync(counts, c->out_cnt, nq * 4, kind, c->stream));
+    if (offsets) {
+        if (c->var_k) {
+            HIP_OR_FAIL(c, hipMemcpyAsync(offsets, c->offsets, (nq + 1) * 8, kind, c->stream));
+        } else if (where == MKNN_HOST) {
+            for (size_t i = 0; i <= nq; ++i) offsets[i] = (int64_t)i * c->k_uniform;
+        } else {
+            std::vector<int64_t> h(nq + 1);
+            for (size_t i = 0; i <= nq; ++i) h[i] = (int64_t)i * c->k_uniform;
+            HIP_OR_FAIL(c, hipMemcpyAsync(offsets, h.data(), (nq + 1) * 8,
+                                          hipMemcpyHostToDevice, c->stream));
+            HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+        }
+    }
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    return MKNN_OK;
+}
+
+int mknn_index_fetch(mknn_ctx *c, uint32_t *codes, int32_t *ids, int32_t *level, uint32_t *prefix,
+                     int64_t *begin, int64_t *end, int64_t leaf_cap, int64_t *n_leaves)
+{
+    if (!c) return MKNN_E_INVAL;
+    if (!c->ticked) return fail(c, MKNN_E_STATE, "no index yet%s");
+    int rc = mknn_sync(c);
+    if (rc) return rc;
+    IndexCounters h{};
+    rc = read_counters(c, &h);
+    if (rc) return rc;
+    const int64_t n = c->n, nl = c->n > 0 ? h.n_leaves : 0;
+    if (n_leaves) *n_leaves = nl;
+    std::vector<Point> pts((size_t)n);
+    if (n) HIP_OR_FAIL(c, hipMemcpy(pts.data(), c->ix.pts, (size_t)n * sizeof(Point),
+                                    hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < n; ++i) {
+        if (codes) codes[i] = pts[(size_t)i].code;
+        if (ids) ids[i] = (int32_t)pts[(size_t)i].id;
+    }
+    if (nl > leaf_cap) return fail(c, MKNN_E_CAPACITY, "leaf_cap too small%s");
+    std::vector<int32_t> lb((size_t)nl), le((size_t)nl), lv((size_t)nl);
+    if (nl) {
+        HIP_OR_FAIL(c, hipMemcpy(lb.data(), c->ix.leaf_begin, (size_t)nl * 4, hipMemcpyDeviceToHost));
+        HIP_OR_FAIL(c, hipMemcpy(le.data(), c->ix.leaf_end, (size_t)nl * 4, hipMemcpyDeviceToHost));
+        HIP_OR_FAIL(c, hipMemcpy(lv.data(), c->ix.leaf_level, (size_t)nl * 4, hipMemcpyDeviceToHost));
+    }
+    for (int64_t j = 0; j < nl; ++j) {
+        if (level) level[j] = lv[(size_t)j];
+        if (begin) begin[j] = lb[(size_t)j];
+        if (end) end[j] = le[(size_t)j];
+        if (prefix) {
+            const int l = lv[(size_t)j];
+            const uint32_t code = pts[(size_t)lb[(size_t)j]].code;
+            prefix[j] = l <= 0 ? 0u : code >> (2 * (kCodeLevels - l));
+        }
+    }
+    return MKNN_OK;
+}
+
+int mknn_get_stats(const mknn_ctx *cc, mknn_stats *out)
+{
+    mknn_ctx *c = const_cast<mknn_ctx *>(cc);
+    if (!c || !out) return MKNN_E_INVAL;
+    memset(out, 0, sizeof *out);
+    out->tick = c->ticks;
+    out->n = c->n;
+    out->nq = c->queried ? c->nq : 0;
+    out->leaf_capacity = c->th;
+    if (c->ticked && !c->dead) {
+        IndexCounters h{};
+        int rc = read_counters(c, &h);
+        if (rc) return rc;
+        out->leaves = c->n > 0 ? h.n_leaves : 0;
+        out->nodes = c->n > 0 ? h.n_nodes : 0;
+        out->deepest_level = (int32_t)h.deepest_level;
+        if ((c->cfg.flags & MKNN_FLAG_TIMING) && c->have_events) {
+            float ms = 0;
+            if (hipEventElapsedTime(&ms, c->ev[0], c->ev[1]) == hipSuccess) out->ms_build = ms;
+            if (c->queried) {
+                if (hipEventElapsedTime(&ms, c->ev[2], c->ev[3]) == hipSuccess) out->ms_query = ms;
+                if (hipEventElapsedTime(&ms, c->ev[4], c->ev[5]) == hipSuccess)
+                    out->ms_query_main = ms;
+            }
+            (void)hipGetLastError();
+        }
+    }
+    return MKNN_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,311 @@
+// Iterative k-NN query processing (arXiv 1412.6170, Sec. 4.2), gfx950.
+//
+// Queries are processed in Morton order of their centres, 64 per
+// wavefront (one query per lane), so the queries of one wavefront are
+// spatial neighbours, as the paper groups the queries of one leaf into one
+// task.  Each lane keeps its current best keys (d2 bits << 32 | id) sorted
+// in registers; the k-th key bounds what can still enter.
+//
+//   1. First iteration: every object of the leaves holding the wavefront's
+//      queries is a candidate (Sec. 4.2.1, distance computations).
+//   2. Subsequent iterations: two sub-visits leave the own leaves in Morton
+//      order, one towards higher codes and one towards lower codes, taking
+//      turns (Sec. 4.2.2).  A quadtree node is entered only if, for some
+//      lane, the lower bound of d2 to the node's box is not above that
+//      lane's k-th distance; otherwise the walk jumps over its subtree
+//      (the node tables are depth-first with subtree-skip links, so the walk
+//      needs neither a stack nor a lookup table).  A reached leaf is swept:
+//      every lane evaluates every object of the leaf.
+//
+// The paper runs each iteration as separate kernels with a host loop and
+// re-sorts the active queries between iterations; here a wavefront carries
+// its 64 queries through all iterations without leaving the kernel, so no
+// active-query sort or host round trip is needed and every candidate leaf is
+// read with wave-uniform (scalar) loads.
+//
+// Exactness.  d2 = fl(fl(dx*dx) + fl(dy*dy)) with no contraction (this file
+// is built with -ffp-contract=off and the pragma below).  A box is skipped
+// only when its lower bound -- the same rounded operations applied to the
+// nearest box edge -- is strictly above the k-th d2; rounding is monotone,
+// so no object of a skipped box could have entered.  Keys order by (d2, id),
+// so the kept set is exactly the first k of Definition 1 with id tie-breaks.
+#include <float.h>
+
+#include "mknn_internal.hpp"
+#include "query.hpp"
+
+#pragma clang fp contract(off)
+
+namespace mknn {
+
+constexpr uint64_t kKeyMax = ~0ull;
+
+__device__ __forceinline__ float sq_dist(float qx, float qy, float px, float py)
+{
+    const float dx = qx - px;
+    const float dy = qy - py;
+    const float ax = dx * dx;
+    const float ay = dy * dy;
+    return ax + ay;
+}
+
+__device__ __forceinline__ float box_lower_bound(float qx, float qy, const Node &nd)
+{
+    const float gx = (qx < nd.x0) ? (nd.x0 - qx) : ((qx >= nd.x1) ? (qx - nd.x1) : 0.0f);
+    const float gy = (qy < nd.y0) ? (nd.y0 - qy) : ((qy >= nd.y1) ? (qy - nd.y1) : 0.0f);
+    const float ax = gx * gx;
+    const float ay = gy * gy;
+    return ax + ay;
+}
+
+__device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
+
+// Lane-private sorted list of the K best keys.  A lane asking for k < K
+// keeps K-k permanent zero sentinels at the bottom, so its k-th key is
+// always list[K-1] and one template serves a mix of k.
+template <int K>
+struct TopK {
+    uint64_t a[K];
+
+    __device__ __forceinline__ void init(int k)
+    {
+#pragma unroll
+        for (int s = 0; s < K; ++s) a[s] = (s < K - k) ? 0ull : kKeyMax;
+    }
+
+    // Insert key (caller guarantees key < a[K-1]); the largest key drops
+    // out.  Branch-free: runs under the caller's execution mask, so lanes
+    // without a hit are untouched.  Walks from the top so a[s-1] is still
+    // the old value when a[s] is rewritten.
+    __device__ __forceinline__ void insert(uint64_t key)
+    {
+        bool below = true;  // key < a[s] for the current s (true at s = K-1)
+#pragma unroll
+        for (int s = K - 1; s >= 1; --s) {
+            const bool below_prev = key < a[s - 1];
+            a[s] = below_prev ? a[s - 1] : (below ? key : a[s]);
+            below = below_prev;
+        }
+        a[0] = below ? key : a[0];
+    }
+};
+
+template <int K>
+struct Lane {
+    float qx, qy;
+    uint32_t self;
+    bool active;
+    uint32_t kth_hi;  // d2 bits of the current k-th key
+    TopK<K> top;
+
+    __device__ __forceinline__ void refresh() { kth_hi = (uint32_t)(top.a[K - 1] >> 32); }
+
+    __device__ __forceinline__ void consider(const Point &p)
+    {
+        const float d2 = sq_dist(qx, qy, p.x, p.y);
+        const uint32_t db = __float_as_uint(d2);
+        if (active && db <= kth_hi && p.id != self) {
+            const uint64_t key = ((uint64_t)db << 32) | p.id;
+            if (key < top.a[K - 1]) {
+                top.insert(key);
+                refresh();
+            }
+        }
+    }
+
+    // Every lane evaluates every object of the sorted range [b, e).  The
+    // range is wave-uniform, so objects arrive through scalar loads; the
+    // next object is requested before the current one is used.
+    __device__ __forceinline__ void sweep(const Point *__restrict__ pts, int32_t b, int32_t e)
+    {
+        if (b >= e) return;
+        Point c = pts[b];
+        for (int32_t j = b; j < e; ++j) {
+            const Point nx = pts[j + 1 < e ? j + 1 : j];
+            consider(c);
+            c = nx;
+        }
+    }
+
+    __device__ __forceinline__ bool wants(const Node &nd) const
+    {
+        return active && __float_as_uint(box_lower_bound(qx, qy, nd)) <= kth_hi;
+    }
+};
+
+// Advance one sub-visit to the next leaf some lane still needs and sweep
+// it.  Returns the walk position after that leaf (or total when done).
+// Positions only move forward (a skip link never points back) and sweep
+// ranges are clamped to the object array, so the walk always terminates
+// inside its buffers.
+template <int K>
+__device__ __forceinline__ int32_t walk_step(Lane<K> &ln, const Node *__restrict__ tab,
+                                             int32_t pos, int32_t total,
+                                             const Point *__restrict__ pts, int32_t n)
+{
+    while (pos < total) {
+        const Node nd = tab[pos];
+        const int32_t next = nd.skip > pos ? nd.skip : pos + 1;
+        if (!wave_any(ln.wants(nd))) {
+            pos = next;
+            continue;
+        }
+        if (nd.leaf >= 0) {
+            ln.sweep(pts, max(nd.begin, 0), min(nd.end, n));
+            return next;
+        }
+        ++pos;
+    }
+    return total;
+}
+
+template <int K>
+__global__ __launch_bounds__(256) void k_knn_tiles(QueryArgs qa)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint32_t tile = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    const uint32_t t = tile * kWave + lane;
+    if (tile * kWave >= qa.nq) return;  // whole wavefront idle
+
+    Lane<K> ln;
+    ln.active = t < qa.nq;
+    const uint32_t tq = ln.active ? t : qa.nq - 1;
+    const int32_t qp = qa.qpos ? qa.qpos[tq] : (int32_t)tq;
+    const Point q = qa.pts[qp];
+    ln.qx = q.x;
+    ln.qy = q.y;
+    ln.self = q.id;
+    const int32_t row = qa.qrow ? qa.qrow[tq] : (int32_t)q.id;
+    int kq = qa.ks ? qa.ks[row] : qa.k_uniform;
+    kq = kq < 1 ? 1 : (kq > K ? K : kq);
+    ln.top.init(kq);
+    ln.refresh();
+
+    // Own leaves of the wavefront's queries: a contiguous run of leaves.
+    const int32_t my_leaf = qa.leaf_of[qp];
+    int32_t l0 = my_leaf, l1 = my_leaf;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        l0 = min(l0, __shfl_xor(l0, d, kWave));
+        l1 = max(l1, __shfl_xor(l1, d, kWave));
+    }
+    l0 = __builtin_amdgcn_readfirstlane(l0);
+    l1 = __builtin_amdgcn_readfirstlane(l1);
+
+    // First iteration: the own leaves.
+    ln.sweep(qa.pts, max(qa.leaf_begin[l0], 0), min(qa.leaf_end[l1], (int32_t)qa.n));
+
+    // Subsequent iterations: alternate the two sub-visits.
+    const int32_t total = min((int32_t)qa.ctr->n_nodes, qa.node_cap);
+    int32_t rf = qa.leaf_node_f[l1] + 1;
+    int32_t rl = qa.leaf_node_r[l0] + 1;
+    bool right = true;
+    while (rf < total || rl < total) {
+        // One code path for both directions (the table is picked uniformly),
+        // so the list is not duplicated across two inlined sweeps.
+        const bool fw = (right && rf < total) || rl >= total;
+        const int32_t pos =
+            walk_step<K>(ln, fw ? qa.fwd : qa.rev, fw ? rf : rl, total, qa.pts, (int32_t)qa.n);
+        rf = fw ? pos : rf;
+        rl = fw ? rl : pos;
+        right = !right;
+    }
+
+    if (!ln.active) return;
+    const int64_t off = qa.row_off ? qa.row_off[row] : (int64_t)row * qa.k_uniform;
+    int32_t *__restrict__ oi = qa.out_ids + off;
+    float *__restrict__ od = qa.out_d2 + off;
+    int cnt = 0;
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+        const int slot = s - (K - kq);
+        if (slot >= 0) {
+            const uint64_t v = ln.top.a[s];
+            const bool real = v != kKeyMax;
+            oi[slot] = real ? (int32_t)(uint32_t)v : -1;
+            od[slot] = real ? __uint_as_float((uint32_t)(v >> 32)) : __builtin_inff();
+            cnt += real ? 1 : 0;
+        }
+    }
+    qa.out_cnt[row] = cnt;
+}
+
+int k_class(int k)
+{
+    if (k <= 8) return 8;
+    if (k <= 16) return 16;
+    if (k <= 32) return 32;
+    if (k <= 64) return 64;
+    return 128;
+}
+
+void launch_knn(const QueryArgs &qa, int kclass, hipStream_t s)
+{
+    if (qa.nq == 0) return;
+    const uint32_t tiles = (qa.nq + kWave - 1) / kWave;
+    const uint32_t waves_per_block = 4;
+    const uint32_t blocks = (tiles + waves_per_block - 1) / waves_per_block;
+    const dim3 grid(blocks), block(waves_per_block * kWave);
+    switch (kclass) {
+    case 8: k_knn_tiles<8><<<grid, block, 0, s>>>(qa); break;
+    case 16: k_knn_tiles<16><<<grid, block, 0, s>>>(qa); break;
+    case 32: k_knn_tiles<32><<<grid, block, 0, s>>>(qa); break;
+    case 64: k_knn_tiles<64><<<grid, block, 0, s>>>(qa); break;
+    default: k_knn_tiles<128><<<grid, block, 0, s>>>(qa); break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Query indexing for a subset of issuers (Sec. 4.2.1, query indexing): sort
+// the queries by their centre's sorted position so wavefronts hold spatial
+// neighbours.  Device-supplied issuers and ks are range-checked here.
+// ---------------------------------------------------------------------------
+
+__global__ void k_query_keys(const int32_t *__restrict__ issuers, const int32_t *__restrict__ ks,
+                             uint32_t nq, uint32_t n, int k_max, const int32_t *__restrict__ inv,
+                             uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
+                             uint32_t *__restrict__ kcount, IndexCounters *__restrict__ ctr)
+{
+    uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nq) return;
+    if (issuers) {
+        int32_t s = issuers[q];
+        bool ok = s >= 0 && (uint32_t)s < n;
+        if (!ok) atomicOr(&ctr->bad_input, 2u);
+        keys[q] = ok ? (uint32_t)inv[s] : 0u;
+        vals[q] = q;
+    }
+    if (ks) {
+        int32_t k = ks[q];
+        bool ok = k >= 1 && k <= k_max;
+        if (!ok) atomicOr(&ctr->bad_input, 4u);
+        kcount[q] = ok ? (uint32_t)k : 1u;
+    }
+}
+
+__global__ void k_widen_offsets(const uint32_t *__restrict__ excl, const uint32_t *__restrict__ total,
+                                uint32_t nq, int64_t *__restrict__ off)
+{
+    uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < nq) off[q] = (int64_t)excl[q];
+    if (q == 0) off[nq] = (int64_t)*total;
+}
+
+void launch_query_prep(const QueryPrep &p, hipStream_t s)
+{
+    const int T = 256;
+    const uint32_t g = (p.nq + T - 1) / T;
+    if (p.nq == 0) return;
+    k_query_keys<<<g, T, 0, s>>>(p.issuers, p.ks, p.nq, p.n, p.k_max, p.inv, p.sort.keys[0],
+                                 p.sort.vals[0], p.kcount, p.ctr);
+}
+
+void launch_offsets(const uint32_t *kcount, uint32_t nq, uint32_t *scan_out, uint32_t *scan_tmp,
+                    uint32_t *total, int64_t *offsets, hipStream_t s)
+{
+    launch_exclusive_scan(kcount, scan_out, nq, scan_tmp, total, s);
+    const int T = 256;
+    k_widen_offsets<<<(nq + 1 + T - 1) / T, T, 0, s>>>(scan_out, total, nq, offsets);
+}
+
+}  // namespace mknn

@@ -1,0 +1,47 @@
+// Arguments of the query kernels (see query.hip).
+#pragma once
+
+#include "mknn_internal.hpp"
+
+namespace mknn {
+
+struct QueryArgs {
+    const Point *pts;            // sorted objects
+    uint32_t n;                  // number of objects
+    const Node *fwd, *rev;       // depth-first node tables
+    const int32_t *leaf_of;      // leaf of each sorted position
+    const int32_t *leaf_begin, *leaf_end;
+    const int32_t *leaf_node_f, *leaf_node_r;
+    const IndexCounters *ctr;
+    int32_t node_cap;            // entries in each node table
+    const int32_t *qpos;         // sorted position of each query centre, in
+                                 // processing order; null = identity
+    const int32_t *qrow;         // result row of each query, processing
+                                 // order; null = object id (every object queries)
+    uint32_t nq;
+    const int32_t *ks;           // k per result row (range-checked); null = k_uniform
+    int32_t k_uniform;
+    const int64_t *row_off;      // first entry of each row; null = row * k_uniform
+    int32_t *out_ids;
+    float *out_d2;
+    int32_t *out_cnt;
+};
+
+struct QueryPrep {
+    const int32_t *issuers;      // device, nq entries, or null
+    const int32_t *ks;           // device, nq entries, or null
+    uint32_t nq, n;
+    int k_max;
+    const int32_t *inv;
+    SortBuffers sort;            // keys[0]/vals[0] receive (sorted position, query)
+    uint32_t *kcount;            // range-checked k per query
+    IndexCounters *ctr;
+};
+
+int k_class(int k);
+void launch_knn(const QueryArgs &qa, int kclass, hipStream_t s);
+void launch_query_prep(const QueryPrep &p, hipStream_t s);
+void launch_offsets(const uint32_t *kcount, uint32_t nq, uint32_t *scan_out, uint32_t *scan_tmp,
+                    uint32_t *total, int64_t *offsets, hipStream_t s);
+
+}  // namespace mknn

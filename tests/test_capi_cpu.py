@@ -1,0 +1,71 @@
+"""CPU-only checks of the C ABI library: it loads and exports every entry
+point include/mknn.h declares, and its pure host helpers behave.  No call
+here touches a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1412_6170_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    with open(os.path.join(ROOT, "include", "mknn.h")) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"MKNN_API\s+[\w\s\*]+?\b(mknn_\w+)\s*\(", text)))
+
+
+def test_header_declares_the_four_verbs_and_helpers():
+    syms = declared_symbols()
+    for verb in ("mknn_load_positions", "mknn_advance_tick", "mknn_query", "mknn_fetch",
+                 "mknn_create", "mknn_destroy", "mknn_sync", "mknn_get_stats",
+                 "mknn_last_error", "mknn_status_str", "mknn_result_size",
+                 "mknn_result_device", "mknn_index_fetch", "mknn_default_leaf_capacity"):
+        assert verb in syms
+
+
+def test_library_exports_every_declared_symbol():
+    lib = binding.lib()
+    raw = ctypes.CDLL(binding.LIB_PATH)
+    for name in declared_symbols():
+        assert hasattr(raw, name), name
+    assert lib is not None
+
+
+def test_status_strings_and_leaf_rule():
+    lib = binding.lib()
+    for code, name in binding.STATUS.items():
+        assert lib.mknn_status_str(code).decode() == name
+    assert lib.mknn_status_str(-99).decode() == "MKNN_E_UNKNOWN"
+    assert binding.default_leaf_capacity(8) == 192
+    assert binding.default_leaf_capacity(32) == 384
+    assert binding.default_leaf_capacity(128) == 1536
+    assert binding.default_leaf_capacity(200) == 2048
+
+
+def test_null_arguments_are_rejected_without_a_device():
+    lib = binding.lib()
+    assert lib.mknn_create(None, None) == -1
+    out = ctypes.c_void_p(1)
+    assert lib.mknn_create(None, ctypes.byref(out)) == -1 and out.value is None
+    assert lib.mknn_destroy(None) == 0
+    assert lib.mknn_advance_tick(None) == -1
+    assert lib.mknn_sync(None) == -1
+    assert lib.mknn_last_error(None).decode() == "null context"
+    cfg = binding.Config()
+    cfg.n_max, cfg.q_max, cfg.k_max = 10, 10, 0      # k_max out of range
+    assert lib.mknn_create(ctypes.byref(cfg), ctypes.byref(out)) == -1
+    cfg.k_max = binding.MKNN_K_LIMIT + 1
+    assert lib.mknn_create(ctypes.byref(cfg), ctypes.byref(out)) == -1
+    cfg.k_max, cfg.max_level = 8, 17
+    assert lib.mknn_create(ctypes.byref(cfg), ctypes.byref(out)) == -1
+
+
+def test_missing_library_raises(monkeypatch):
+    monkeypatch.setattr(binding, "_lib", None)
+    monkeypatch.setattr(binding, "LIB_PATH", "/nonexistent/libmknn.so")
+    with pytest.raises(ImportError):
+        binding.lib()
