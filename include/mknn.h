@@ -103,10 +103,15 @@ typedef struct mknn_stats {
     int64_t nodes;         /* quadtree nodes kept (inner + non-empty leaves) */
     int32_t leaf_capacity; /* th used for the current index */
     int32_t deepest_level; /* l_deep: deepest leaf level (Sec. 4.1) */
-    float ms_build;        /* device time of the index build (MKNN_FLAG_TIMING) */
-    float ms_query;        /* device time of the query, all kernels */
-    float ms_query_main;   /* device time of the leaf-sweep kernel alone */
-    float reserved[5];
+    float ms_build;        /* device time of the last index build (MKNN_FLAG_TIMING) */
+    float ms_query;        /* device time of the last query, all kernels */
+    float ms_query_main;   /* device time of the last query's leaf-sweep kernel */
+    int32_t timed_ticks;   /* builds and queries timed since mknn_reset_timing
+                              (at most the last 256 of each are kept) */
+    float ms_build_mean;   /* means over those ticks */
+    float ms_query_mean;
+    float ms_query_main_mean;
+    float reserved[4];
 } mknn_stats;
 
 /*
@@ -206,6 +211,10 @@ MKNN_API int mknn_sync(mknn_ctx *ctx);
 /* mknn_get_stats -- counters of the current index and last query; device
  * times need MKNN_FLAG_TIMING and a prior mknn_sync. */
 MKNN_API int mknn_get_stats(const mknn_ctx *ctx, mknn_stats *out);
+
+/* mknn_reset_timing -- forget the device times recorded so far (the means
+ * in mknn_stats restart). */
+MKNN_API int mknn_reset_timing(mknn_ctx *ctx);
 
 /* mknn_last_error -- message of the context's last error ("" if none). */
 MKNN_API const char *mknn_last_error(const mknn_ctx *ctx);

@@ -35,7 +35,9 @@ class Stats(ctypes.Structure):
                 ("leaves", ctypes.c_int64), ("nodes", ctypes.c_int64),
                 ("leaf_capacity", ctypes.c_int32), ("deepest_level", ctypes.c_int32),
                 ("ms_build", ctypes.c_float), ("ms_query", ctypes.c_float),
-                ("ms_query_main", ctypes.c_float), ("reserved", ctypes.c_float * 5)]
+                ("ms_query_main", ctypes.c_float), ("timed_ticks", ctypes.c_int32),
+                ("ms_build_mean", ctypes.c_float), ("ms_query_mean", ctypes.c_float),
+                ("ms_query_main_mean", ctypes.c_float), ("reserved", ctypes.c_float * 4)]
 
 
 class MknnError(RuntimeError):
@@ -71,6 +73,7 @@ def lib():
             "mknn_index_fetch": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64,
                                   ctypes.POINTER(_i64)], _i32),
             "mknn_sync": ([_vp], _i32),
+            "mknn_reset_timing": ([_vp], _i32),
             "mknn_get_stats": ([_vp, ctypes.POINTER(Stats)], _i32),
             "mknn_last_error": ([_vp], ctypes.c_char_p),
             "mknn_status_str": ([_i32], ctypes.c_char_p),
@@ -222,6 +225,9 @@ class Context:
 
     def sync(self):
         self._check(lib().mknn_sync(self._h))
+
+    def reset_timing(self):
+        self._check(lib().mknn_reset_timing(self._h))
 
     def stats(self):
         s = Stats()

@@ -41,6 +41,11 @@ struct mknn_ctx {
 
     hipEvent_t ev[6]{};
     bool have_events = false;
+    // Rings of event pairs for per-tick means: [slot][0..5] as ev above.
+    static constexpr int kRing = 256;
+    hipEvent_t ring[kRing][6]{};
+    bool have_ring = false;
+    int64_t ring_build = 0, ring_query = 0;   // calls recorded since reset
     std::vector<void *> allocs;
 };
 
@@ -102,6 +107,10 @@ int bits_for(int64_t n)
 
 __global__ void k_reset_counters(IndexCounters *ctr) { *ctr = IndexCounters{}; }
 
+// Query-side error bits (bad issuer, bad k) belong to one query; the
+// coordinate bit belongs to the snapshot and stays until the next load.
+__global__ void k_clear_query_flags(IndexCounters *ctr) { ctr->bad_input &= ~6u; }
+
 int read_counters(mknn_ctx *c, IndexCounters *h)
 {
     HIP_OR_FAIL(c, hipMemcpyAsync(h, c->ix.ctr, sizeof *h, hipMemcpyDeviceToHost, c->stream));
@@ -124,6 +133,18 @@ int check_deferred(mknn_ctx *c)
 }
 
 bool valid_where(int32_t w) { return w == MKNN_HOST || w == MKNN_DEVICE; }
+
+// Record event i (0..5, same meaning as mknn_ctx::ev) for timing.
+int mark(mknn_ctx *c, int i)
+{
+    if (!((c->cfg.flags & MKNN_FLAG_TIMING) && c->have_events)) return MKNN_OK;
+    HIP_OR_FAIL(c, hipEventRecord(c->ev[i], c->stream));
+    if (c->have_ring) {
+        const int64_t slot = (i < 2 ? c->ring_build : c->ring_query) % mknn_ctx::kRing;
+        HIP_OR_FAIL(c, hipEventRecord(c->ring[slot][i], c->stream));
+    }
+    return MKNN_OK;
+}
 
 }  // namespace
 
@@ -163,6 +184,9 @@ int mknn_destroy(mknn_ctx *c)
     for (void *p : c->allocs) (void)hipFree(p);
     if (c->have_events)
         for (auto &e : c->ev) (void)hipEventDestroy(e);
+    for (auto &slot : c->ring)
+        for (auto &e : slot)
+            if (e) (void)hipEventDestroy(e);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     (void)hipSetDevice(dev);
     delete c;
@@ -259,6 +283,12 @@ int mknn_create(const mknn_config *cfg, mknn_ctx **out)
         c->have_events = true;
         for (auto &ev : c->ev)
             if (hipEventCreate(&ev) != hipSuccess) c->have_events = false;
+        if (cfg->flags & MKNN_FLAG_TIMING) {
+            c->have_ring = true;
+            for (auto &slot : c->ring)
+                for (auto &ev : slot)
+                    if (hipEventCreate(&ev) != hipSuccess) c->have_ring = false;
+        }
         k_reset_counters<<<1, 1, 0, c->stream>>>(c->ix.ctr);
         rc = check_launch(c, "reset counters");
     }
@@ -306,13 +336,14 @@ int mknn_advance_tick(mknn_ctx *c)
     if (c->dead) return fail(c, MKNN_E_DEVICE, "context has a sticky device error%s");
     if (!c->loaded) return fail(c, MKNN_E_STATE, "advance_tick before load_positions%s");
     HIP_OR_FAIL(c, hipSetDevice(c->cfg.device));
-    const bool timing = (c->cfg.flags & MKNN_FLAG_TIMING) && c->have_events;
-    if (timing) HIP_OR_FAIL(c, hipEventRecord(c->ev[0], c->stream));
+    int rc = mark(c, 0);
+    if (rc) return rc;
     k_reset_counters<<<1, 1, 0, c->stream>>>(c->ix.ctr);
     launch_build_index(c->ix, c->x, c->y, c->n, c->th, c->L, c->stream);
-    int rc = check_launch(c, "index build");
+    rc = check_launch(c, "index build");
+    if (!rc) rc = mark(c, 1);
     if (rc) return rc;
-    if (timing) HIP_OR_FAIL(c, hipEventRecord(c->ev[1], c->stream));
+    ++c->ring_build;
     c->ticked = true;
     c->queried = false;
     ++c->ticks;
@@ -350,9 +381,10 @@ int mknn_query(mknn_ctx *c, const int32_t *issuers, const int32_t *ks, int64_t n
         if (ks) kmax_call = kmx;
     }
     HIP_OR_FAIL(c, hipSetDevice(c->cfg.device));
-    const bool timing = (c->cfg.flags & MKNN_FLAG_TIMING) && c->have_events;
-    if (timing) HIP_OR_FAIL(c, hipEventRecord(c->ev[2], c->stream));
+    int rc = mark(c, 2);
+    if (rc) return rc;
 
+    k_clear_query_flags<<<1, 1, 0, c->stream>>>(c->ix.ctr);
     const int32_t *d_iss = issuers, *d_ks = ks;
     if (where == MKNN_HOST && nq > 0) {
         if (issuers) {
@@ -413,14 +445,14 @@ int mknn_query(mknn_ctx *c, const int32_t *issuers, const int32_t *ks, int64_t n
         launch_offsets(c->kcount, 0, c->kscan, c->ix.sort.scan_tmp, c->ktotal, c->offsets,
                        c->stream);
     }
-    if (timing) HIP_OR_FAIL(c, hipEventRecord(c->ev[4], c->stream));
-    launch_knn(qa, k_class(kmax_call), c->stream);
-    int rc = check_launch(c, "k-NN query");
+    rc = mark(c, 4);
     if (rc) return rc;
-    if (timing) {
-        HIP_OR_FAIL(c, hipEventRecord(c->ev[5], c->stream));
-        HIP_OR_FAIL(c, hipEventRecord(c->ev[3], c->stream));
-    }
+    launch_knn(qa, k_class(kmax_call), c->stream);
+    rc = check_launch(c, "k-NN query");
+    if (!rc) rc = mark(c, 5);
+    if (!rc) rc = mark(c, 3);
+    if (rc) return rc;
+    ++c->ring_query;
     c->queried = true;
     c->nq = nq;
     c->var_k = ks != nullptr;
@@ -553,6 +585,16 @@ int mknn_index_fetch(mknn_ctx *c, uint32_t *codes, int32_t *ids, int32_t *level,
     return MKNN_OK;
 }
 
+int mknn_reset_timing(mknn_ctx *c)
+{
+    if (!c) return MKNN_E_INVAL;
+    int rc = mknn_sync(c);
+    if (rc) return rc;
+    c->ring_build = 0;
+    c->ring_query = 0;
+    return MKNN_OK;
+}
+
 int mknn_get_stats(const mknn_ctx *cc, mknn_stats *out)
 {
     mknn_ctx *c = const_cast<mknn_ctx *>(cc);
@@ -576,6 +618,23 @@ int mknn_get_stats(const mknn_ctx *cc, mknn_stats *out)
                 if (hipEventElapsedTime(&ms, c->ev[2], c->ev[3]) == hipSuccess) out->ms_query = ms;
                 if (hipEventElapsedTime(&ms, c->ev[4], c->ev[5]) == hipSuccess)
                     out->ms_query_main = ms;
+            }
+            if (c->have_ring) {
+                const int64_t nb = c->ring_build < mknn_ctx::kRing ? c->ring_build : mknn_ctx::kRing;
+                const int64_t nqr = c->ring_query < mknn_ctx::kRing ? c->ring_query : mknn_ctx::kRing;
+                double sb = 0, sq = 0, sm = 0;
+                for (int64_t i = 0; i < nb; ++i)
+                    if (hipEventElapsedTime(&ms, c->ring[i][0], c->ring[i][1]) == hipSuccess) sb += ms;
+                for (int64_t i = 0; i < nqr; ++i) {
+                    if (hipEventElapsedTime(&ms, c->ring[i][2], c->ring[i][3]) == hipSuccess) sq += ms;
+                    if (hipEventElapsedTime(&ms, c->ring[i][4], c->ring[i][5]) == hipSuccess) sm += ms;
+                }
+                out->timed_ticks = (int32_t)(nb < nqr ? nb : nqr);
+                if (nb) out->ms_build_mean = (float)(sb / nb);
+                if (nqr) {
+                    out->ms_query_mean = (float)(sq / nqr);
+                    out->ms_query_main_mean = (float)(sm / nqr);
+                }
             }
             (void)hipGetLastError();
         }
