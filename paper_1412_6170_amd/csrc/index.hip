@@ -110,8 +110,10 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *total)
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t *__restrict__ in,
                                                              uint32_t n,
-                                                             uint32_t *__restrict__ sums)
+                                                             uint32_t *__restrict__ sums,
+                                                             const uint32_t *__restrict__ n_dev)
 {
+    if (n_dev) n = min(n, *n_dev);
     const uint32_t base = blockIdx.x * (uint32_t)kScanTile;
     uint32_t s = 0;
 #pragma unroll
@@ -151,8 +153,11 @@ __global__ __launch_bounds__(1024) void k_scan_top(uint32_t *__restrict__ sums, 
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t *in, uint32_t *out,
                                                            uint32_t n,
-                                                           const uint32_t *__restrict__ sums)
+                                                           const uint32_t *__restrict__ sums,
+                                                           const uint32_t *__restrict__ n_dev)
 {
+    if (n_dev) n = min(n, *n_dev);
+    if (blockIdx.x * (uint32_t)kScanTile >= n) return;
     // Blocked arrangement: thread t owns kScanItems consecutive elements.
     const uint32_t base = blockIdx.x * (uint32_t)kScanTile + threadIdx.x * (uint32_t)kScanItems;
     uint32_t v[kScanItems], s = 0;
@@ -176,16 +181,16 @@ int64_t scan_tmp_elems(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; 
 __global__ void k_store_zero(uint32_t *p) { *p = 0u; }
 
 void launch_exclusive_scan(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp,
-                           uint32_t *total, hipStream_t s)
+                           uint32_t *total, hipStream_t s, const uint32_t *n_dev)
 {
     if (n <= 0) {
         if (total) k_store_zero<<<1, 1, 0, s>>>(total);
         return;
     }
     uint32_t nb = (uint32_t)((n + kScanTile - 1) / kScanTile);
-    k_scan_reduce<<<nb, kScanThreads, 0, s>>>(in, (uint32_t)n, tmp);
+    k_scan_reduce<<<nb, kScanThreads, 0, s>>>(in, (uint32_t)n, tmp, n_dev);
     k_scan_top<<<1, 1024, 0, s>>>(tmp, nb, total);
-    k_scan_down<<<nb, kScanThreads, 0, s>>>(in, out, (uint32_t)n, tmp);
+    k_scan_down<<<nb, kScanThreads, 0, s>>>(in, out, (uint32_t)n, tmp, n_dev);
 }
 
 // ---------------------------------------------------------------------------
@@ -367,13 +372,16 @@ __global__ void k_gather(const uint32_t *__restrict__ keys, const uint32_t *__re
 }
 
 // flags[0] = 1; flags[i+1] = 1 iff sorted objects i and i+1 lie in different
-// leaves.  The quadrant holding both is found by walking outwards over the
-// sorted codes while they share its prefix; the walk stops as soon as it
-// has seen more than th objects, so it costs O(min(quadrant size, th)).
+// leaves, i.e. iff the deepest quadrant holding both (level c) is split:
+// c < L and the quadrant holds more than th objects.  The quadrant is a run
+// [lo, hi] of the sorted codes; it holds more than th objects iff
+// codes[lo + th] still lies in it.  lo is found by a binary search over the
+// last th positions up to i (if the run starts even earlier, the search
+// returns i + 1 - th and the test still holds, since then i + 1 = lo + th).
 __global__ void k_leaf_flags(const uint32_t *__restrict__ codes, uint32_t n, int th, int L,
                              uint32_t *__restrict__ flags)
 {
-    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     if (i == 0) flags[0] = 1u;
     if (i + 1 >= n) return;
@@ -381,22 +389,21 @@ __global__ void k_leaf_flags(const uint32_t *__restrict__ codes, uint32_t n, int
     const int c = common_level(a, b);
     uint32_t split = 0;
     if (c < L) {
-        int64_t size = 2, lo = i, hi = (int64_t)i + 1;
-        while (size <= th) {
-            bool grew = false;
-            if (lo > 0 && same_quadrant(codes[lo - 1], a, c)) {
-                --lo;
-                ++size;
-                grew = true;
+        int64_t first = (int64_t)i + 1 - th;
+        if (first < 0) first = 0;
+        int64_t count = (int64_t)i - first;  // positions before i still to test
+        while (count > 0) {
+            const int64_t step = count >> 1;
+            const int64_t mid = first + step;
+            if (!same_quadrant(codes[mid], a, c)) {
+                first = mid + 1;
+                count -= step + 1;
+            } else {
+                count = step;
             }
-            if (size <= th && hi + 1 < (int64_t)n && same_quadrant(codes[hi + 1], a, c)) {
-                ++hi;
-                ++size;
-                grew = true;
-            }
-            if (!grew) break;
         }
-        split = size > th ? 1u : 0u;
+        const int64_t last = first + th;
+        split = (last < (int64_t)n && same_quadrant(codes[last], a, c)) ? 1u : 0u;
     }
     flags[i + 1] = split;
 }
@@ -428,13 +435,12 @@ __global__ void k_leaf_info(const uint32_t *__restrict__ codes, uint32_t n, int 
                             int32_t *__restrict__ leaf_level, uint32_t *__restrict__ cnt_f,
                             uint32_t *__restrict__ cnt_r)
 {
-    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t nl = ctr->n_leaves;
+    const uint32_t j0 = blockIdx.x * blockDim.x;
+    if (j0 >= nl) return;  // whole block past the last leaf
+    const uint32_t j = j0 + threadIdx.x;
     int lev = 0;
-    if (j < n && j >= nl) {
-        cnt_f[j] = 0;
-        cnt_r[j] = 0;
-    } else if (j < nl) {
+    if (j < nl) {
         const int32_t b = leaf_begin[j], e = leaf_end[j];
         const int cl = b > 0 ? common_level(codes[b - 1], codes[b]) : -1;
         const int cr = (uint32_t)e < n ? common_level(codes[e - 1], codes[e]) : -1;
@@ -443,11 +449,11 @@ __global__ void k_leaf_info(const uint32_t *__restrict__ codes, uint32_t n, int 
         cnt_f[j] = (uint32_t)(lev - cl);
         cnt_r[j] = (uint32_t)(lev - cr);
     }
-    // Statistic only: one atomic per wavefront.
+    // Statistic only: one atomic per wavefront that holds leaves.
     int deepest = lev;
 #pragma unroll
     for (int d = 1; d < kWave; d <<= 1) deepest = max(deepest, __shfl_xor(deepest, d, kWave));
-    if ((threadIdx.x & (kWave - 1)) == 0) atomicMax(&ctr->deepest_level, (uint32_t)deepest);
+    if ((threadIdx.x & (kWave - 1)) == 0 && j < nl) atomicMax(&ctr->deepest_level, (uint32_t)deepest);
 }
 
 __device__ __forceinline__ void node_box(uint32_t code, int l, Node &nd)
@@ -462,6 +468,10 @@ __device__ __forceinline__ void node_box(uint32_t code, int l, Node &nd)
     nd.y1 = (float)(cy + side) * s;
 }
 
+// One work item per (leaf j, slot s): slot s of leaf j's forward nodes is
+// its ancestor at level cl+1+s (the leaf itself for the last slot), slot s
+// of its backward nodes the ancestor at level cr+1+s.  Inner nodes find the
+// end of their subtree by a binary search over the leaves' first codes.
 __global__ void k_node_emit(const uint32_t *__restrict__ codes, uint32_t n,
                             const int32_t *__restrict__ leaf_begin,
                             const int32_t *__restrict__ leaf_end,
@@ -471,80 +481,86 @@ __global__ void k_node_emit(const uint32_t *__restrict__ codes, uint32_t n,
                             Node *__restrict__ rev, int32_t *__restrict__ leaf_node_f,
                             int32_t *__restrict__ leaf_node_r, uint32_t node_cap)
 {
-    uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    constexpr uint32_t kSlots = kCodeLevels + 1;
     const uint32_t nl = ctr->n_leaves;
-    if (j >= nl) return;
     const uint32_t total = ctr->n_nodes;
     if (total > node_cap) {
         // Cannot happen for a correct build (the capacity bounds the tree);
         // refuse to write rather than overrun.
-        if (j == 0) atomicOr(&ctr->bad_input, 8u);
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&ctr->bad_input, 8u);
         return;
     }
-    const int32_t b = leaf_begin[j], e = leaf_end[j];
-    const int lev = leaf_level[j];
-    const uint32_t code = codes[b];
-    const int cl = b > 0 ? common_level(codes[b - 1], codes[b]) : -1;
-    const int cr = (uint32_t)e < n ? common_level(codes[e - 1], codes[e]) : -1;
-    // Backward table offset: nodes of all later leaves come first.
-    const uint32_t rbase = total - off_r[j] - (uint32_t)(lev - cr);
+    const uint64_t items = (uint64_t)nl * kSlots;
+    for (uint64_t it = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; it < items;
+         it += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t j = (uint32_t)(it / kSlots);
+        const int sl = (int)(it % kSlots);
+        const int32_t b = leaf_begin[j], e = leaf_end[j];
+        const int lev = leaf_level[j];
+        const uint32_t code = codes[b];
+        const int cl = b > 0 ? common_level(codes[b - 1], codes[b]) : -1;
+        const int cr = (uint32_t)e < n ? common_level(codes[e - 1], codes[e]) : -1;
 
-    for (int l = cl + 1; l <= lev; ++l) {
-        Node nd;
-        node_box(code, l, nd);
-        const uint32_t idx = off_f[j] + (uint32_t)(l - cl - 1);
-        if (l == lev) {
-            nd.begin = b;
-            nd.end = e;
-            nd.skip = (int32_t)idx + 1;
-            nd.leaf = (int32_t)j;
-            leaf_node_f[j] = (int32_t)idx;
-        } else {
-            // First later leaf outside this quadrant (leaves sorted by code).
-            uint32_t lo = j + 1, hi = nl;
-            while (lo < hi) {
-                uint32_t mid = (lo + hi) >> 1;
-                if (same_quadrant(codes[leaf_begin[mid]], code, l)) lo = mid + 1;
-                else hi = mid;
-            }
-            nd.begin = b;
-            nd.end = lo < nl ? leaf_begin[lo] : (int32_t)n;
-            nd.skip = lo < nl ? (int32_t)off_f[lo] : (int32_t)total;
-            nd.leaf = -1;
-        }
-        if (idx < node_cap) fwd[idx] = nd;
-    }
-    for (int l = cr + 1; l <= lev; ++l) {
-        Node nd;
-        node_box(code, l, nd);
-        const uint32_t idx = rbase + (uint32_t)(l - cr - 1);
-        if (l == lev) {
-            nd.begin = b;
-            nd.end = e;
-            nd.skip = (int32_t)idx + 1;
-            nd.leaf = (int32_t)j;
-            leaf_node_r[j] = (int32_t)idx;
-        } else {
-            // First (lowest) leaf inside this quadrant.
-            uint32_t lo = 0, hi = j;
-            while (lo < hi) {
-                uint32_t mid = (lo + hi) >> 1;
-                if (same_quadrant(codes[leaf_begin[mid]], code, l)) hi = mid;
-                else lo = mid + 1;
-            }
-            nd.begin = leaf_begin[lo];
-            nd.end = e;
-            if (lo > 0) {
-                const int32_t pb = leaf_begin[lo - 1], pe = leaf_end[lo - 1];
-                const int pcr = common_level(codes[pe - 1], codes[pe]);
-                nd.skip = (int32_t)(total - off_r[lo - 1] - (uint32_t)(leaf_level[lo - 1] - pcr));
-                (void)pb;
+        const int lf = cl + 1 + sl;  // forward level of this slot
+        if (lf <= lev) {
+            Node nd;
+            node_box(code, lf, nd);
+            const uint32_t idx = off_f[j] + (uint32_t)sl;
+            if (lf == lev) {
+                nd.begin = b;
+                nd.end = e;
+                nd.skip = (int32_t)idx + 1;
+                nd.leaf = (int32_t)j;
+                leaf_node_f[j] = (int32_t)idx;
             } else {
-                nd.skip = (int32_t)total;
+                // First later leaf outside this quadrant.
+                uint32_t lo = j + 1, hi = nl;
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (same_quadrant(codes[leaf_begin[mid]], code, lf)) lo = mid + 1;
+                    else hi = mid;
+                }
+                nd.begin = b;
+                nd.end = lo < nl ? leaf_begin[lo] : (int32_t)n;
+                nd.skip = lo < nl ? (int32_t)off_f[lo] : (int32_t)total;
+                nd.leaf = -1;
             }
-            nd.leaf = -1;
+            if (idx < node_cap) fwd[idx] = nd;
         }
-        if (idx < node_cap) rev[idx] = nd;
+        const int lr = cr + 1 + sl;  // backward level of this slot
+        if (lr <= lev) {
+            Node nd;
+            node_box(code, lr, nd);
+            // Backward table: nodes of all later leaves come first.
+            const uint32_t rbase = total - off_r[j] - (uint32_t)(lev - cr);
+            const uint32_t idx = rbase + (uint32_t)sl;
+            if (lr == lev) {
+                nd.begin = b;
+                nd.end = e;
+                nd.skip = (int32_t)idx + 1;
+                nd.leaf = (int32_t)j;
+                leaf_node_r[j] = (int32_t)idx;
+            } else {
+                // First (lowest) leaf inside this quadrant.
+                uint32_t lo = 0, hi = j;
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (same_quadrant(codes[leaf_begin[mid]], code, lr)) hi = mid;
+                    else lo = mid + 1;
+                }
+                nd.begin = leaf_begin[lo];
+                nd.end = e;
+                if (lo > 0) {
+                    const int32_t pe = leaf_end[lo - 1];
+                    const int pcr = common_level(codes[pe - 1], codes[pe]);
+                    nd.skip = (int32_t)(total - off_r[lo - 1] - (uint32_t)(leaf_level[lo - 1] - pcr));
+                } else {
+                    nd.skip = (int32_t)total;
+                }
+                nd.leaf = -1;
+            }
+            if (idx < node_cap) rev[idx] = nd;
+        }
     }
 }
 
@@ -582,9 +598,10 @@ void launch_build_index(IndexBuffers &b, const float *x, const float *y, int64_t
     k_leaf_emit<<<g, T, 0, s>>>(b.flags, excl, nn, b.leaf_of, b.leaf_begin, b.leaf_end);
     k_leaf_info<<<g, T, 0, s>>>(codes, nn, th, L, b.leaf_begin, b.leaf_end, b.ctr, b.leaf_level,
                                 b.cnt_f, b.cnt_r);
-    launch_exclusive_scan(b.cnt_f, b.cnt_f, n, b.sort.scan_tmp, &b.ctr->n_nodes, s);
-    launch_exclusive_scan(b.cnt_r, b.cnt_r, n, b.sort.scan_tmp, nullptr, s);
-    k_node_emit<<<g, T, 0, s>>>(codes, nn, b.leaf_begin, b.leaf_end, b.leaf_level, b.cnt_f,
+    launch_exclusive_scan(b.cnt_f, b.cnt_f, n, b.sort.scan_tmp, &b.ctr->n_nodes, s,
+                          &b.ctr->n_leaves);
+    launch_exclusive_scan(b.cnt_r, b.cnt_r, n, b.sort.scan_tmp, nullptr, s, &b.ctr->n_leaves);
+    k_node_emit<<<1024, T, 0, s>>>(codes, nn, b.leaf_begin, b.leaf_end, b.leaf_level, b.cnt_f,
                                 b.cnt_r, b.ctr, b.fwd, b.rev, b.leaf_node_f, b.leaf_node_r,
                                 (uint32_t)b.node_cap);
 }

@@ -79,8 +79,9 @@ struct IndexBuffers {
 int64_t scan_tmp_elems(int64_t n);
 // Exclusive scan of n uint32 values (in -> out may alias); *total, if not
 // null, receives the sum on the device.
+// If n_dev is given, only the first min(n, *n_dev) entries are scanned.
 void launch_exclusive_scan(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp,
-                           uint32_t *total, hipStream_t s);
+                           uint32_t *total, hipStream_t s, const uint32_t *n_dev = nullptr);
 
 // Number of histogram entries a radix sort of n keys needs.
 int64_t radix_hist_elems(int64_t n);

@@ -60,57 +60,116 @@ __device__ __forceinline__ float box_lower_bound(float qx, float qy, const Node 
 
 __device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
 
-// Lane-private sorted list of the K best keys.  A lane asking for k < K
-// keeps K-k permanent zero sentinels at the bottom, so its k-th key is
-// always list[K-1] and one template serves a mix of k.
-template <int K>
-struct TopK {
-    uint64_t a[K];
+// Compare-exchange on keys: afterwards lo <= hi.
+__device__ __forceinline__ void cmp_swap(uint64_t &lo, uint64_t &hi)
+{
+    const bool s = lo > hi;
+    const uint64_t t = s ? hi : lo;
+    hi = s ? lo : hi;
+    lo = t;
+}
 
-    __device__ __forceinline__ void init(int k)
+// Bitonic sorting network on a register array (all indices static).
+template <int N>
+__device__ __forceinline__ void bitonic_sort(uint64_t (&b)[N])
+{
+#pragma unroll
+    for (int size = 2; size <= N; size <<= 1) {
+#pragma unroll
+        for (int stride = size / 2; stride > 0; stride >>= 1) {
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                const int j = i ^ stride;
+                if (j > i) {
+                    if ((i & size) == 0) cmp_swap(b[i], b[j]);
+                    else cmp_swap(b[j], b[i]);
+                }
+            }
+        }
+    }
+}
+
+// Sort a bitonic register array ascending (half-cleaner cascade).
+template <int N>
+__device__ __forceinline__ void bitonic_merge(uint64_t (&a)[N])
+{
+#pragma unroll
+    for (int stride = N / 2; stride > 0; stride >>= 1) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            const int j = i ^ stride;
+            if (j > i) cmp_swap(a[i], a[j]);
+        }
+    }
+}
+
+// Lane-private selection of the K best keys (d2 bits << 32 | id).
+//
+// a[] holds the current best, sorted, in registers.  A lane asking for
+// k < K keeps K-k permanent zero sentinels at the bottom, so its k-th key is
+// always a[K-1] and one template serves a mix of k.
+//
+// Candidates below the lane's threshold are not inserted one by one (in a
+// wavefront every lane would pay for any lane's insertion); they are
+// appended to a lane-private queue of P keys in LDS.  When some lane's
+// queue is full -- and once at the end -- every lane merges its queue into
+// a[]: the queue is sorted with a bitonic network, the lower K keys of
+// a[] and the queue are taken with one min against the reversed queue
+// (which leaves a bitonic sequence) and a bitonic merge sorts them.
+// The threshold is refreshed at each merge; between merges it may be
+// stale, which only lets more keys into the queue.
+template <int K, int P>
+struct Selector {
+    uint64_t a[K];
+    uint64_t *q;       // this lane's queue: q[s * kWave], s < P
+    uint32_t cnt;
+    uint64_t thr;      // a[K-1] at the last merge
+
+    __device__ __forceinline__ void init(int k, uint64_t *lane_queue)
     {
 #pragma unroll
         for (int s = 0; s < K; ++s) a[s] = (s < K - k) ? 0ull : kKeyMax;
+        q = lane_queue;
+        cnt = 0;
+        thr = kKeyMax;
     }
 
-    // Insert key (caller guarantees key < a[K-1]); the largest key drops
-    // out.  Branch-free: runs under the caller's execution mask, so lanes
-    // without a hit are untouched.  Walks from the top so a[s-1] is still
-    // the old value when a[s] is rewritten.
-    __device__ __forceinline__ void insert(uint64_t key)
+    __device__ __forceinline__ void push(uint64_t key)
     {
-        bool below = true;  // key < a[s] for the current s (true at s = K-1)
+        q[cnt * kWave] = key;
+        ++cnt;
+    }
+
+    __device__ __forceinline__ void merge()
+    {
+        uint64_t b[P];
 #pragma unroll
-        for (int s = K - 1; s >= 1; --s) {
-            const bool below_prev = key < a[s - 1];
-            a[s] = below_prev ? a[s - 1] : (below ? key : a[s]);
-            below = below_prev;
-        }
-        a[0] = below ? key : a[0];
+        for (int s = 0; s < P; ++s) b[s] = (uint32_t)s < cnt ? q[s * kWave] : kKeyMax;
+        bitonic_sort<P>(b);
+#pragma unroll
+        for (int i = K - P; i < K; ++i) a[i] = min(a[i], b[K - 1 - i]);
+        bitonic_merge<K>(a);
+        cnt = 0;
+        thr = a[K - 1];
     }
 };
 
-template <int K>
+template <int K, int P>
 struct Lane {
     float qx, qy;
     uint32_t self;
     bool active;
-    uint32_t kth_hi;  // d2 bits of the current k-th key
-    TopK<K> top;
-
-    __device__ __forceinline__ void refresh() { kth_hi = (uint32_t)(top.a[K - 1] >> 32); }
+    Selector<K, P> sel;
 
     __device__ __forceinline__ void consider(const Point &p)
     {
         const float d2 = sq_dist(qx, qy, p.x, p.y);
         const uint32_t db = __float_as_uint(d2);
-        if (active && db <= kth_hi && p.id != self) {
+        if (active && db <= (uint32_t)(sel.thr >> 32) && p.id != self) {
             const uint64_t key = ((uint64_t)db << 32) | p.id;
-            if (key < top.a[K - 1]) {
-                top.insert(key);
-                refresh();
-            }
+            if (key < sel.thr) sel.push(key);
         }
+        if (wave_any(sel.cnt == (uint32_t)P)) sel.merge();
     }
 
     // Every lane evaluates every object of the sorted range [b, e).  The
@@ -127,19 +186,21 @@ struct Lane {
         }
     }
 
+    // A node is needed if its box may hold a key below some lane's
+    // threshold (queued keys are not yet counted, so this errs on the side
+    // of visiting).
     __device__ __forceinline__ bool wants(const Node &nd) const
     {
-        return active && __float_as_uint(box_lower_bound(qx, qy, nd)) <= kth_hi;
+        return active &&
+               __float_as_uint(box_lower_bound(qx, qy, nd)) <= (uint32_t)(sel.thr >> 32);
     }
 };
 
-// Advance one sub-visit to the next leaf some lane still needs and sweep
-// it.  Returns the walk position after that leaf (or total when done).
 // Positions only move forward (a skip link never points back) and sweep
 // ranges are clamped to the object array, so the walk always terminates
 // inside its buffers.
-template <int K>
-__device__ __forceinline__ int32_t walk_step(Lane<K> &ln, const Node *__restrict__ tab,
+template <int K, int P>
+__device__ __forceinline__ int32_t walk_step(Lane<K, P> &ln, const Node *__restrict__ tab,
                                              int32_t pos, int32_t total,
                                              const Point *__restrict__ pts, int32_t n)
 {
@@ -159,15 +220,17 @@ __device__ __forceinline__ int32_t walk_step(Lane<K> &ln, const Node *__restrict
     return total;
 }
 
-template <int K>
+template <int K, int P>
 __global__ __launch_bounds__(256) void k_knn_tiles(QueryArgs qa)
 {
+    __shared__ uint64_t s_queue[256 / kWave][P * kWave];
     const int lane = threadIdx.x & (kWave - 1);
-    const uint32_t tile = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    const int wib = threadIdx.x / kWave;
+    const uint32_t tile = blockIdx.x * (blockDim.x / kWave) + wib;
     const uint32_t t = tile * kWave + lane;
     if (tile * kWave >= qa.nq) return;  // whole wavefront idle
 
-    Lane<K> ln;
+    Lane<K, P> ln;
     ln.active = t < qa.nq;
     const uint32_t tq = ln.active ? t : qa.nq - 1;
     const int32_t qp = qa.qpos ? qa.qpos[tq] : (int32_t)tq;
@@ -178,8 +241,7 @@ __global__ __launch_bounds__(256) void k_knn_tiles(QueryArgs qa)
     const int32_t row = qa.qrow ? qa.qrow[tq] : (int32_t)q.id;
     int kq = qa.ks ? qa.ks[row] : qa.k_uniform;
     kq = kq < 1 ? 1 : (kq > K ? K : kq);
-    ln.top.init(kq);
-    ln.refresh();
+    ln.sel.init(kq, &s_queue[wib][lane]);
 
     // Own leaves of the wavefront's queries: a contiguous run of leaves.
     const int32_t my_leaf = qa.leaf_of[qp];
@@ -199,17 +261,21 @@ __global__ __launch_bounds__(256) void k_knn_tiles(QueryArgs qa)
     const int32_t total = min((int32_t)qa.ctr->n_nodes, qa.node_cap);
     int32_t rf = qa.leaf_node_f[l1] + 1;
     int32_t rl = qa.leaf_node_r[l0] + 1;
+    rf = (rf < 1 || rf > total) ? total : rf;
+    rl = (rl < 1 || rl > total) ? total : rl;
     bool right = true;
     while (rf < total || rl < total) {
         // One code path for both directions (the table is picked uniformly),
         // so the list is not duplicated across two inlined sweeps.
         const bool fw = (right && rf < total) || rl >= total;
         const int32_t pos =
-            walk_step<K>(ln, fw ? qa.fwd : qa.rev, fw ? rf : rl, total, qa.pts, (int32_t)qa.n);
+            walk_step<K, P>(ln, fw ? qa.fwd : qa.rev, fw ? rf : rl, total, qa.pts, (int32_t)qa.n);
         rf = fw ? pos : rf;
         rl = fw ? rl : pos;
         right = !right;
     }
+
+    if (wave_any(ln.sel.cnt > 0)) ln.sel.merge();
 
     if (!ln.active) return;
     const int64_t off = qa.row_off ? qa.row_off[row] : (int64_t)row * qa.k_uniform;
@@ -220,7 +286,7 @@ __global__ __launch_bounds__(256) void k_knn_tiles(QueryArgs qa)
     for (int s = 0; s < K; ++s) {
         const int slot = s - (K - kq);
         if (slot >= 0) {
-            const uint64_t v = ln.top.a[s];
+            const uint64_t v = ln.sel.a[s];
             const bool real = v != kKeyMax;
             oi[slot] = real ? (int32_t)(uint32_t)v : -1;
             od[slot] = real ? __uint_as_float((uint32_t)(v >> 32)) : __builtin_inff();
@@ -247,11 +313,11 @@ void launch_knn(const QueryArgs &qa, int kclass, hipStream_t s)
     const uint32_t blocks = (tiles + waves_per_block - 1) / waves_per_block;
     const dim3 grid(blocks), block(waves_per_block * kWave);
     switch (kclass) {
-    case 8: k_knn_tiles<8><<<grid, block, 0, s>>>(qa); break;
-    case 16: k_knn_tiles<16><<<grid, block, 0, s>>>(qa); break;
-    case 32: k_knn_tiles<32><<<grid, block, 0, s>>>(qa); break;
-    case 64: k_knn_tiles<64><<<grid, block, 0, s>>>(qa); break;
-    default: k_knn_tiles<128><<<grid, block, 0, s>>>(qa); break;
+    case 8: k_knn_tiles<8, 8><<<grid, block, 0, s>>>(qa); break;
+    case 16: k_knn_tiles<16, 16><<<grid, block, 0, s>>>(qa); break;
+    case 32: k_knn_tiles<32, 16><<<grid, block, 0, s>>>(qa); break;
+    case 64: k_knn_tiles<64, 16><<<grid, block, 0, s>>>(qa); break;
+    default: k_knn_tiles<128, 16><<<grid, block, 0, s>>>(qa); break;
     }
 }
 
