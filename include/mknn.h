@@ -74,7 +74,8 @@ extern "C" {
 #define MKNN_K_LIMIT 128
 
 /* mknn_config.flags */
-#define MKNN_FLAG_TIMING 1 /* record per-phase device times (mknn_stats) */
+#define MKNN_FLAG_TIMING 1   /* record per-phase device times (mknn_stats) */
+#define MKNN_FLAG_COUNTERS 2 /* count the query kernel's work (mknn_stats) */
 
 typedef struct mknn_ctx mknn_ctx;
 
@@ -112,6 +113,12 @@ typedef struct mknn_stats {
     float ms_query_mean;
     float ms_query_main_mean;
     float reserved[4];
+    /* MKNN_FLAG_COUNTERS: totals over the queries since mknn_reset_timing */
+    int64_t wave_candidate_steps; /* candidates evaluated, counted once per wavefront */
+    int64_t wave_merges;          /* queue merges, once per wavefront */
+    int64_t wave_node_visits;     /* node-table entries examined, once per wavefront */
+    int64_t wave_leaf_sweeps;     /* leaves swept, once per wavefront */
+    int64_t wavefronts;           /* query wavefronts run */
 } mknn_stats;
 
 /*
@@ -122,6 +129,10 @@ typedef struct mknn_stats {
  */
 MKNN_API int mknn_create(const mknn_config *cfg, mknn_ctx **out);
 
+/* mknn_footprint -- device bytes mknn_create would allocate for cfg (no
+ * device is touched), for admission decisions.  Errors: MKNN_E_INVAL. */
+MKNN_API int mknn_footprint(const mknn_config *cfg, int64_t *bytes);
+
 /* mknn_destroy -- wait for the context's work and free everything.  NULL is
  * allowed.  A borrowed stream is left alone. */
 MKNN_API int mknn_destroy(mknn_ctx *ctx);
@@ -130,8 +141,10 @@ MKNN_API int mknn_destroy(mknn_ctx *ctx);
  * mknn_load_positions -- replace the snapshot with n objects (Sec. 2.2:
  * only the latest update of each object counts).  x[i], y[i] is object i's
  * position, two arrays of n floats, host or device memory per `where`.
- * The data is copied; host arrays may be reused when the call returns,
- * device arrays once the context's stream has reached the copy.
+ * Host arrays are copied into the context and may be reused when the call
+ * returns.  Device arrays are not copied: the index build reads them in
+ * place, so they must stay valid and unchanged until the context's stream
+ * has passed the next mknn_advance_tick.
  * Host input is validated during the call (MKNN_E_RANGE leaves the previous
  * snapshot in place).  Device input is validated on the device; a bad value
  * makes the next mknn_sync / mknn_fetch return MKNN_E_RANGE.
@@ -158,6 +171,12 @@ MKNN_API int mknn_advance_tick(mknn_ctx *ctx);
  * device memory per `where`; they are read before the call returns (host)
  * or once the stream reaches the query (device).  Results stay on the device,
  * owned by the context, until the next mknn_query.
+ * Graph capture: a load/advance/query sequence with device inputs enqueues
+ * kernels only, so it may be captured on the context's stream and
+ * replayed.  The context's host-side description of the results (nq, k,
+ * entries, used by mknn_fetch and mknn_result_size) is that of the last
+ * call made on the host; after replaying a captured query, issue no eager
+ * query of a different shape on the context before fetching.
  * Errors: MKNN_E_INVAL (bad issuer or k, host-side), MKNN_E_STATE (no tick
  * since the last load), MKNN_E_CAPACITY (nq > q_max or, for variable k, the
  * sum of ks above q_max * k_max).
@@ -212,8 +231,18 @@ MKNN_API int mknn_sync(mknn_ctx *ctx);
  * times need MKNN_FLAG_TIMING and a prior mknn_sync. */
 MKNN_API int mknn_get_stats(const mknn_ctx *ctx, mknn_stats *out);
 
-/* mknn_reset_timing -- forget the device times recorded so far (the means
- * in mknn_stats restart). */
+/*
+ * mknn_set_leaf_capacity -- use leaf capacity th (Sec. 4.1) for the next
+ * index builds.  The node tables were sized at mknn_create for the
+ * configured capacity; a smaller th may need more nodes, so th below the
+ * configured value returns MKNN_E_CAPACITY unless the tables still fit
+ * (create with the smallest th you intend to use).  Results never depend on
+ * th.  Errors: MKNN_E_INVAL (th < 1), MKNN_E_CAPACITY.
+ */
+MKNN_API int mknn_set_leaf_capacity(mknn_ctx *ctx, int32_t th);
+
+/* mknn_reset_timing -- forget the device times and counters recorded so far
+ * (the means and totals in mknn_stats restart). */
 MKNN_API int mknn_reset_timing(mknn_ctx *ctx);
 
 /* mknn_last_error -- message of the context's last error ("" if none). */

@@ -17,6 +17,7 @@ MKNN_OK = 0
 MKNN_HOST = 0
 MKNN_DEVICE = 1
 MKNN_FLAG_TIMING = 1
+MKNN_FLAG_COUNTERS = 2
 MKNN_K_LIMIT = 128
 STATUS = {0: "MKNN_OK", -1: "MKNN_E_INVAL", -2: "MKNN_E_RANGE", -3: "MKNN_E_STATE",
           -4: "MKNN_E_CAPACITY", -5: "MKNN_E_NOMEM", -6: "MKNN_E_DEVICE"}
@@ -37,7 +38,10 @@ class Stats(ctypes.Structure):
                 ("ms_build", ctypes.c_float), ("ms_query", ctypes.c_float),
                 ("ms_query_main", ctypes.c_float), ("timed_ticks", ctypes.c_int32),
                 ("ms_build_mean", ctypes.c_float), ("ms_query_mean", ctypes.c_float),
-                ("ms_query_main_mean", ctypes.c_float), ("reserved", ctypes.c_float * 4)]
+                ("ms_query_main_mean", ctypes.c_float), ("reserved", ctypes.c_float * 4),
+                ("wave_candidate_steps", ctypes.c_int64), ("wave_merges", ctypes.c_int64),
+                ("wave_node_visits", ctypes.c_int64), ("wave_leaf_sweeps", ctypes.c_int64),
+                ("wavefronts", ctypes.c_int64)]
 
 
 class MknnError(RuntimeError):
@@ -74,10 +78,12 @@ def lib():
                                   ctypes.POINTER(_i64)], _i32),
             "mknn_sync": ([_vp], _i32),
             "mknn_reset_timing": ([_vp], _i32),
+            "mknn_set_leaf_capacity": ([_vp, _i32], _i32),
             "mknn_get_stats": ([_vp, ctypes.POINTER(Stats)], _i32),
             "mknn_last_error": ([_vp], ctypes.c_char_p),
             "mknn_status_str": ([_i32], ctypes.c_char_p),
             "mknn_default_leaf_capacity": ([_i32], _i32),
+            "mknn_footprint": ([ctypes.POINTER(Config), ctypes.POINTER(_i64)], _i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -87,8 +93,45 @@ def lib():
     return _lib
 
 
+_hiplib = None
+
+
+def _hip():
+    """The HIP runtime, for plain device-to-host copies of result rows."""
+    global _hiplib
+    if _hiplib is None:
+        _hiplib = ctypes.CDLL("libamdhip64.so")
+        _hiplib.hipMemcpy.argtypes = [_vp, _vp, ctypes.c_size_t, ctypes.c_int]
+        _hiplib.hipMemcpy.restype = ctypes.c_int
+    return _hiplib
+
+
 def default_leaf_capacity(k):
     return int(lib().mknn_default_leaf_capacity(int(k)))
+
+
+def make_config(n_max, q_max=None, k_max=32, leaf_capacity=0, max_level=0, k_hint=0, device=0,
+                stream=None, timing=False, counters=False):
+    cfg = Config()
+    cfg.device = device
+    cfg.leaf_capacity = int(leaf_capacity)
+    cfg.max_level = int(max_level)
+    cfg.k_max = int(k_max)
+    cfg.n_max = int(n_max)
+    cfg.q_max = int(q_max if q_max is not None else n_max)
+    cfg.stream = stream
+    cfg.k_hint = int(k_hint)
+    cfg.flags = (MKNN_FLAG_TIMING if timing else 0) | (MKNN_FLAG_COUNTERS if counters else 0)
+    return cfg
+
+
+def footprint(**kw):
+    """Device bytes a context with these settings allocates (no device use)."""
+    b = _i64()
+    rc = lib().mknn_footprint(ctypes.byref(make_config(**kw)), ctypes.byref(b))
+    if rc != 0:
+        raise MknnError(rc, "mknn_footprint failed")
+    return b.value
 
 
 def _is_tensor(a):
@@ -104,17 +147,9 @@ class Context:
     of up to k_max neighbours each."""
 
     def __init__(self, n_max, q_max=None, k_max=32, leaf_capacity=0, max_level=0, k_hint=0,
-                 device=0, stream=None, timing=False):
-        cfg = Config()
-        cfg.device = device
-        cfg.leaf_capacity = int(leaf_capacity)
-        cfg.max_level = int(max_level)
-        cfg.k_max = int(k_max)
-        cfg.n_max = int(n_max)
-        cfg.q_max = int(q_max if q_max is not None else n_max)
-        cfg.stream = stream
-        cfg.k_hint = int(k_hint)
-        cfg.flags = MKNN_FLAG_TIMING if timing else 0
+                 device=0, stream=None, timing=False, counters=False):
+        cfg = make_config(n_max, q_max, k_max, leaf_capacity, max_level, k_hint, device, stream,
+                          timing, counters)
         self.cfg = cfg
         h = _vp()
         rc = lib().mknn_create(ctypes.byref(cfg), ctypes.byref(h))
@@ -174,6 +209,7 @@ class Context:
             raise ValueError("x and y differ in length")
         self._check(lib().mknn_load_positions(self._h, px, py, n, wx))
         self._keep = [kx, ky]
+        self._n = n
 
     def advance_tick(self):
         self._check(lib().mknn_advance_tick(self._h))
@@ -190,7 +226,7 @@ class Context:
             elif kk is not None:
                 nq = len(kk)
             else:
-                nq = self.stats()["n"]
+                nq = self._n
         self._check(lib().mknn_query(self._h, pi, pk, int(nq), int(k or 0), where))
         self._qkeep = [ki, kk]
         self._last_k = None if ks is not None else int(k)
@@ -217,6 +253,26 @@ class Context:
             return ids.reshape(nq, k), d2.reshape(nq, k), cnt, None
         return ids, d2, cnt, off
 
+    def fetch_rows(self, rows, k):
+        """Host copies of selected rows of a uniform-k result (ids, d2,
+        counts), copied row by row from the device."""
+        hip = _hip()
+        ids_p, d2_p, cnt_p, _ = self.result_device_ptrs()
+        self.sync()
+        rows = np.asarray(rows, np.int64)
+        ids = np.empty((len(rows), k), np.int32)
+        d2 = np.empty((len(rows), k), np.float32)
+        cnt = np.empty(len(rows), np.int32)
+        for i, r in enumerate(rows):
+            for dst, src, size, off in ((ids[i], ids_p, 4 * k, 4 * k * int(r)),
+                                        (d2[i], d2_p, 4 * k, 4 * k * int(r)),
+                                        (cnt[i:i + 1], cnt_p, 4, 4 * int(r))):
+                rc = hip.hipMemcpy(dst.ctypes.data_as(_vp), ctypes.c_void_p(src + off),
+                                   ctypes.c_size_t(size), 2)  # device to host
+                if rc != 0:
+                    raise MknnError(-6, "hipMemcpy failed (%d)" % rc)
+        return ids, d2, cnt
+
     def result_device_ptrs(self):
         ids, d2, cnt, off = _vp(), _vp(), _vp(), _vp()
         self._check(lib().mknn_result_device(self._h, ctypes.byref(ids), ctypes.byref(d2),
@@ -228,6 +284,9 @@ class Context:
 
     def reset_timing(self):
         self._check(lib().mknn_reset_timing(self._h))
+
+    def set_leaf_capacity(self, th):
+        self._check(lib().mknn_set_leaf_capacity(self._h, int(th)))
 
     def stats(self):
         s = Stats()
@@ -254,6 +313,36 @@ class Context:
         m = nl.value
         return {"codes": codes[:n], "ids": ids[:n], "leaf_level": lev[:m], "leaf_prefix": pre[:m],
                 "leaf_begin": beg[:m], "leaf_end": end[:m], "nodes": st["nodes"]}
+
+
+def autotune_leaf_capacity(ctx, run_tick, candidates, repeats=3):
+    """Pick the leaf capacity with the shortest device time per tick.
+
+    ctx must have been created with timing enabled and with a leaf capacity
+    no larger than min(candidates) (the node tables are sized for it).
+    run_tick(i) enqueues tick i (load, advance, query) on the context.  Each
+    candidate runs `repeats` ticks after one untimed tick; the mean of the
+    library's build + query device times decides.  Results never depend on
+    the leaf capacity, only the time does.  Returns (best, {th: ms})."""
+    times = {}
+    i = 0
+    for th in candidates:
+        ctx.set_leaf_capacity(th)
+        run_tick(i)
+        i += 1
+        ctx.sync()
+        ctx.reset_timing()
+        for _ in range(repeats):
+            run_tick(i)
+            i += 1
+        ctx.sync()
+        st = ctx.stats()
+        times[th] = st["ms_build_mean"] + st["ms_query_mean"]
+    best = min(times, key=times.get)
+    ctx.set_leaf_capacity(best)
+    ctx.sync()
+    ctx.reset_timing()
+    return best, times
 
 
 def knn_tick(x, y, k=None, issuers=None, ks=None, leaf_capacity=0, max_level=0, k_max=None):

@@ -24,20 +24,26 @@ struct mknn_ctx {
     std::string err;
 
     bool loaded = false, ticked = false, queried = false;
+    bool inv_ready = false;    // ix.inv matches the current index
     int64_t n = 0, nq = 0, entries = 0;
     int32_t k_uniform = 0;
     bool var_k = false;
     int64_t ticks = 0;
 
-    float *x = nullptr, *y = nullptr;
+    float *x = nullptr, *y = nullptr;           // copies of host-supplied positions
+    const float *src_x = nullptr, *src_y = nullptr;  // positions the next build reads
+    uint32_t build_epoch = 0, query_epoch = 0;  // tags of the device flags
     IndexBuffers ix{};
     SortBuffers qs{};          // query-order sort (subset queries)
+    Workspace qws{};           // its workspace (and the offsets scan's)
+    ScanSpace qscan{};
     int32_t *issuers = nullptr, *ks = nullptr;  // staging of host query arrays
     uint32_t *kcount = nullptr, *kscan = nullptr, *ktotal = nullptr;
     int64_t *offsets = nullptr;
     int32_t *out_ids = nullptr;
     float *out_d2 = nullptr;
     int32_t *out_cnt = nullptr;
+    unsigned long long *counters = nullptr;  // query-kernel work counters [5]
 
     hipEvent_t ev[6]{};
     bool have_events = false;
@@ -107,9 +113,13 @@ int bits_for(int64_t n)
 
 __global__ void k_reset_counters(IndexCounters *ctr) { *ctr = IndexCounters{}; }
 
-// Query-side error bits (bad issuer, bad k) belong to one query; the
-// coordinate bit belongs to the snapshot and stays until the next load.
-__global__ void k_clear_query_flags(IndexCounters *ctr) { ctr->bad_input &= ~6u; }
+// Epochs run 1 .. 2^24-1 (the deepest-level word keeps 8 bits for the level).
+uint32_t next_epoch(uint32_t e) { return e >= (1u << 24) - 1 ? 1u : e + 1u; }
+
+__global__ void k_zero_u64(unsigned long long *p, int n)
+{
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0ull;
+}
 
 int read_counters(mknn_ctx *c, IndexCounters *h)
 {
@@ -124,15 +134,92 @@ int check_deferred(mknn_ctx *c)
     IndexCounters h{};
     int rc = read_counters(c, &h);
     if (rc) return rc;
-    if (h.bad_input & 1u)
+    if (h.bad_coord == c->build_epoch)
         return fail(c, MKNN_E_RANGE, "a device coordinate is not finite or outside [0,1)%s");
-    if (h.bad_input & 2u) return fail(c, MKNN_E_INVAL, "a device issuer is outside [0,n)%s");
-    if (h.bad_input & 4u) return fail(c, MKNN_E_INVAL, "a device k is outside [1,k_max]%s");
-    if (h.bad_input & 8u) return fail(c, MKNN_E_DEVICE, "node table capacity exceeded%s");
+    if (h.bad_nodes == c->build_epoch)
+        return fail(c, MKNN_E_DEVICE, "node table capacity exceeded%s");
+    if (c->queried && h.bad_issuer == c->query_epoch)
+        return fail(c, MKNN_E_INVAL, "a device issuer is outside [0,n)%s");
+    if (c->queried && h.bad_k == c->query_epoch)
+        return fail(c, MKNN_E_INVAL, "a device k is outside [1,k_max]%s");
     return MKNN_OK;
 }
 
 bool valid_where(int32_t w) { return w == MKNN_HOST || w == MKNN_DEVICE; }
+
+// Every device buffer of a context and its element count, in one list:
+// mknn_create allocates from it and mknn_footprint sums it.
+template <class F>
+void for_each_buffer(mknn_ctx *c, F &&f)
+{
+    const int64_t N = c->cfg.n_max, Q = c->cfg.q_max;
+    const int64_t node_cap = c->ix.node_cap;
+    f(c->x, N);
+    f(c->y, N);
+    f(c->ix.sort.keys[0], N);
+    f(c->ix.sort.keys[1], N);
+    f(c->ix.sort.vals[0], N);
+    f(c->ix.sort.vals[1], N);
+    f(c->ix.ws.base, c->ix.ws.cap_words);
+    f(c->qws.base, c->qws.cap_words);
+    f(c->ix.pts, N);
+    f(c->ix.inv, N);
+    f(c->ix.leaf_of, N);
+    f(c->ix.flags, N);
+    f(c->ix.leaf_begin, N);
+    f(c->ix.leaf_end, N);
+    f(c->ix.leaf_level, N);
+    f(c->ix.leaf_code, N);
+    f(c->ix.cnt_f, N);
+    f(c->ix.cnt_r, N);
+    f(c->ix.leaf_node_f, N);
+    f(c->ix.leaf_node_r, N);
+    f(c->ix.fwd, node_cap);
+    f(c->ix.rev, node_cap);
+    f(c->ix.ctr, 1);
+    f(c->qs.keys[0], Q);
+    f(c->qs.keys[1], Q);
+    f(c->qs.vals[0], Q);
+    f(c->qs.vals[1], Q);
+    f(c->issuers, Q);
+    f(c->ks, Q);
+    f(c->kcount, Q);
+    f(c->kscan, Q);
+    f(c->ktotal, 1);
+    f(c->offsets, Q + 1);
+    f(c->out_ids, Q * c->k_max);
+    f(c->out_d2, Q * c->k_max);
+    f(c->out_cnt, Q);
+    f(c->counters, 8);
+}
+
+void size_context(mknn_ctx *c)
+{
+    const int64_t N = c->cfg.n_max, Q = c->cfg.q_max;
+    c->ix.n_cap = N;
+    c->ix.node_cap = node_capacity(N, c->th, c->L);
+    c->ix.ws.cap_words = workspace_words(N);
+    c->qws.cap_words = workspace_words(Q + 1);
+}
+
+bool valid_config(const mknn_config *cfg)
+{
+    return cfg->n_max >= 1 && cfg->n_max < ((int64_t)1 << 31) && cfg->q_max >= 1 &&
+           cfg->q_max < ((int64_t)1 << 31) && cfg->k_max >= 1 && cfg->k_max <= MKNN_K_LIMIT &&
+           cfg->max_level >= 0 && cfg->max_level <= kCodeLevels && cfg->leaf_capacity >= 0 &&
+           cfg->k_hint >= 0 && cfg->k_hint <= MKNN_K_LIMIT;
+}
+
+void configure(mknn_ctx *c, const mknn_config *cfg)
+{
+    c->cfg = *cfg;
+    c->L = cfg->max_level ? cfg->max_level : kCodeLevels;
+    c->k_max = cfg->k_max;
+    const int kh = cfg->k_hint ? cfg->k_hint : cfg->k_max;
+    c->th = cfg->leaf_capacity ? cfg->leaf_capacity : mknn_default_leaf_capacity(kh);
+    size_context(c);
+}
+
 
 // Record event i (0..5, same meaning as mknn_ctx::ev) for timing.
 int mark(mknn_ctx *c, int i)
@@ -193,25 +280,33 @@ int mknn_destroy(mknn_ctx *c)
     return MKNN_OK;
 }
 
+int mknn_footprint(const mknn_config *cfg, int64_t *bytes)
+{
+    if (!cfg || !bytes) return MKNN_E_INVAL;
+    if (!valid_config(cfg)) return MKNN_E_INVAL;
+    mknn_ctx tmp;
+    configure(&tmp, cfg);
+    int64_t total = 0;
+    for_each_buffer(&tmp, [&](auto &p, int64_t count) {
+        if (count < 1) count = 1;
+        // hipMalloc rounds small allocations up; count whole 256-byte units.
+        total += (int64_t)(((size_t)count * sizeof(*p) + 255) / 256 * 256);
+    });
+    *bytes = total;
+    return MKNN_OK;
+}
+
 int mknn_create(const mknn_config *cfg, mknn_ctx **out)
 {
     if (!out) return MKNN_E_INVAL;
     *out = nullptr;
     if (!cfg) return MKNN_E_INVAL;
-    if (cfg->n_max < 1 || cfg->n_max >= ((int64_t)1 << 31) || cfg->q_max < 1 ||
-        cfg->q_max >= ((int64_t)1 << 31) || cfg->k_max < 1 || cfg->k_max > MKNN_K_LIMIT ||
-        cfg->max_level < 0 || cfg->max_level > kCodeLevels || cfg->leaf_capacity < 0 ||
-        cfg->k_hint < 0 || cfg->k_hint > MKNN_K_LIMIT)
-        return MKNN_E_INVAL;
+    if (!valid_config(cfg)) return MKNN_E_INVAL;
     if ((double)cfg->q_max * cfg->k_max >= 4294967295.0) return MKNN_E_CAPACITY;
 
     mknn_ctx *c = new (std::nothrow) mknn_ctx;
     if (!c) return MKNN_E_NOMEM;
-    c->cfg = *cfg;
-    c->L = cfg->max_level ? cfg->max_level : kCodeLevels;
-    c->k_max = cfg->k_max;
-    const int kh = cfg->k_hint ? cfg->k_hint : cfg->k_max;
-    c->th = cfg->leaf_capacity ? cfg->leaf_capacity : mknn_default_leaf_capacity(kh);
+    configure(c, cfg);
 
     hipError_t e = hipSetDevice(cfg->device);
     if (e != hipSuccess) {
@@ -229,56 +324,9 @@ int mknn_create(const mknn_config *cfg, mknn_ctx **out)
         }
         c->own_stream = true;
     }
-    const int64_t N = cfg->n_max, Q = cfg->q_max;
-    const int64_t NQ = N > Q ? N : Q;
-    const int64_t node_cap = node_capacity(N, c->th, c->L);
-    const int64_t hist = radix_hist_elems(NQ);
-    int64_t stmp = scan_tmp_elems(hist);
-    if (scan_tmp_elems(NQ + 1) > stmp) stmp = scan_tmp_elems(NQ + 1);
-    c->ix.n_cap = N;
-    c->ix.node_cap = node_cap;
-    c->ix.hist_cap = hist;
-    c->ix.scan_tmp_cap = stmp;
-#define A(p, cnt)                       \
-    if (!rc) rc = dalloc(c, &(p), (cnt));
-    A(c->x, N);
-    A(c->y, N);
-    A(c->ix.sort.keys[0], N);
-    A(c->ix.sort.keys[1], N);
-    A(c->ix.sort.vals[0], N);
-    A(c->ix.sort.vals[1], N);
-    A(c->ix.sort.hist, hist);
-    A(c->ix.sort.scan_tmp, stmp);
-    A(c->ix.pts, N);
-    A(c->ix.inv, N);
-    A(c->ix.leaf_of, N);
-    A(c->ix.flags, N);
-    A(c->ix.leaf_begin, N);
-    A(c->ix.leaf_end, N);
-    A(c->ix.leaf_level, N);
-    A(c->ix.cnt_f, N);
-    A(c->ix.cnt_r, N);
-    A(c->ix.leaf_node_f, N);
-    A(c->ix.leaf_node_r, N);
-    A(c->ix.fwd, node_cap);
-    A(c->ix.rev, node_cap);
-    A(c->ix.ctr, 1);
-    A(c->qs.keys[0], Q);
-    A(c->qs.keys[1], Q);
-    A(c->qs.vals[0], Q);
-    A(c->qs.vals[1], Q);
-    c->qs.hist = c->ix.sort.hist;
-    c->qs.scan_tmp = c->ix.sort.scan_tmp;
-    A(c->issuers, Q);
-    A(c->ks, Q);
-    A(c->kcount, Q);
-    A(c->kscan, Q);
-    A(c->ktotal, 1);
-    A(c->offsets, Q + 1);
-    A(c->out_ids, Q * c->k_max);
-    A(c->out_d2, Q * c->k_max);
-    A(c->out_cnt, Q);
-#undef A
+    for_each_buffer(c, [&](auto &p, int64_t count) {
+        if (!rc) rc = dalloc(c, &p, count);
+    });
     if (!rc) {
         c->have_events = true;
         for (auto &ev : c->ev)
@@ -290,6 +338,7 @@ int mknn_create(const mknn_config *cfg, mknn_ctx **out)
                     if (hipEventCreate(&ev) != hipSuccess) c->have_ring = false;
         }
         k_reset_counters<<<1, 1, 0, c->stream>>>(c->ix.ctr);
+        k_zero_u64<<<1, 8, 0, c->stream>>>(c->counters, 8);
         rc = check_launch(c, "reset counters");
     }
     if (rc) {
@@ -316,11 +365,20 @@ int mknn_load_positions(mknn_ctx *c, const float *x, const float *y, int64_t n, 
         }
     }
     HIP_OR_FAIL(c, hipSetDevice(c->cfg.device));
-    const hipMemcpyKind kind = where == MKNN_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
-    if (n > 0) {
-        HIP_OR_FAIL(c, hipMemcpyAsync(c->x, x, (size_t)n * sizeof(float), kind, c->stream));
-        HIP_OR_FAIL(c, hipMemcpyAsync(c->y, y, (size_t)n * sizeof(float), kind, c->stream));
-        if (where == MKNN_HOST) HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    if (where == MKNN_HOST) {
+        if (n > 0) {
+            HIP_OR_FAIL(c, hipMemcpyAsync(c->x, x, (size_t)n * sizeof(float),
+                                          hipMemcpyHostToDevice, c->stream));
+            HIP_OR_FAIL(c, hipMemcpyAsync(c->y, y, (size_t)n * sizeof(float),
+                                          hipMemcpyHostToDevice, c->stream));
+            HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+        }
+        c->src_x = c->x;
+        c->src_y = c->y;
+    } else {
+        // Read in place by the next index build.
+        c->src_x = x;
+        c->src_y = y;
     }
     c->n = n;
     c->loaded = true;
@@ -338,14 +396,15 @@ int mknn_advance_tick(mknn_ctx *c)
     HIP_OR_FAIL(c, hipSetDevice(c->cfg.device));
     int rc = mark(c, 0);
     if (rc) return rc;
-    k_reset_counters<<<1, 1, 0, c->stream>>>(c->ix.ctr);
-    launch_build_index(c->ix, c->x, c->y, c->n, c->th, c->L, c->stream);
+    c->build_epoch = next_epoch(c->build_epoch);
+    launch_build_index(c->ix, c->src_x, c->src_y, c->n, c->th, c->L, c->build_epoch, c->stream);
     rc = check_launch(c, "index build");
     if (!rc) rc = mark(c, 1);
     if (rc) return rc;
     ++c->ring_build;
     c->ticked = true;
     c->queried = false;
+    c->inv_ready = false;
     ++c->ticks;
     return MKNN_OK;
 }
@@ -384,7 +443,7 @@ int mknn_query(mknn_ctx *c, const int32_t *issuers, const int32_t *ks, int64_t n
     int rc = mark(c, 2);
     if (rc) return rc;
 
-    k_clear_query_flags<<<1, 1, 0, c->stream>>>(c->ix.ctr);
+    c->query_epoch = next_epoch(c->query_epoch);
     const int32_t *d_iss = issuers, *d_ks = ks;
     if (where == MKNN_HOST && nq > 0) {
         if (issuers) {
@@ -416,8 +475,14 @@ int mknn_query(mknn_ctx *c, const int32_t *issuers, const int32_t *ks, int64_t n
     qa.out_ids = c->out_ids;
     qa.out_d2 = c->out_d2;
     qa.out_cnt = c->out_cnt;
+    qa.counters = (c->cfg.flags & MKNN_FLAG_COUNTERS) ? c->counters : nullptr;
 
+    if (d_iss && nq > 0 && !c->inv_ready) {
+        launch_inverse(c->ix, c->n, c->stream);
+        c->inv_ready = true;
+    }
     if ((d_iss || d_ks) && nq > 0) {
+        const int64_t words = carve_workspace(c->qws, nq + 1, &c->qs, &c->qscan, 1);
         QueryPrep p{};
         p.issuers = d_iss;
         p.ks = d_ks;
@@ -428,6 +493,9 @@ int mknn_query(mknn_ctx *c, const int32_t *issuers, const int32_t *ks, int64_t n
         p.sort = c->qs;
         p.kcount = c->kcount;
         p.ctr = c->ix.ctr;
+        p.ws = c->qws.base;
+        p.ws_words = words;
+        p.epoch = c->query_epoch;
         launch_query_prep(p, c->stream);
         if (d_iss) {
             const int res = launch_radix_sort(c->qs, nq, bits_for(c->n), c->stream);
@@ -435,15 +503,16 @@ int mknn_query(mknn_ctx *c, const int32_t *issuers, const int32_t *ks, int64_t n
             qa.qrow = (const int32_t *)c->qs.vals[res];
         }
         if (d_ks) {
-            launch_offsets(c->kcount, (uint32_t)nq, c->kscan, c->ix.sort.scan_tmp, c->ktotal,
-                           c->offsets, c->stream);
+            launch_offsets(c->kcount, (uint32_t)nq, c->kscan, c->qscan, c->ktotal, c->offsets,
+                           c->stream);
             qa.ks = (const int32_t *)c->kcount;
             qa.row_off = c->offsets;
         }
     } else if (d_ks) {
         // nq == 0 with variable k: a single zero offset.
-        launch_offsets(c->kcount, 0, c->kscan, c->ix.sort.scan_tmp, c->ktotal, c->offsets,
-                       c->stream);
+        const int64_t words = carve_workspace(c->qws, 1, &c->qs, &c->qscan, 1);
+        launch_zero_words(c->qws.base, words, c->stream);
+        launch_offsets(c->kcount, 0, c->kscan, c->qscan, c->ktotal, c->offsets, c->stream);
     }
     rc = mark(c, 4);
     if (rc) return rc;
@@ -585,6 +654,17 @@ int mknn_index_fetch(mknn_ctx *c, uint32_t *codes, int32_t *ids, int32_t *level,
     return MKNN_OK;
 }
 
+int mknn_set_leaf_capacity(mknn_ctx *c, int32_t th)
+{
+    if (!c) return MKNN_E_INVAL;
+    if (th < 1) return fail(c, MKNN_E_INVAL, "leaf capacity must be >= 1%s");
+    if (node_capacity(c->cfg.n_max, th, c->L) > c->ix.node_cap)
+        return fail(c, MKNN_E_CAPACITY, "leaf capacity %s needs larger node tables than allocated",
+                    std::to_string(th).c_str());
+    c->th = th;
+    return MKNN_OK;
+}
+
 int mknn_reset_timing(mknn_ctx *c)
 {
     if (!c) return MKNN_E_INVAL;
@@ -592,7 +672,8 @@ int mknn_reset_timing(mknn_ctx *c)
     if (rc) return rc;
     c->ring_build = 0;
     c->ring_query = 0;
-    return MKNN_OK;
+    k_zero_u64<<<1, 8, 0, c->stream>>>(c->counters, 8);
+    return check_launch(c, "reset counters");
 }
 
 int mknn_get_stats(const mknn_ctx *cc, mknn_stats *out)
@@ -608,9 +689,18 @@ int mknn_get_stats(const mknn_ctx *cc, mknn_stats *out)
         IndexCounters h{};
         int rc = read_counters(c, &h);
         if (rc) return rc;
+        if (c->cfg.flags & MKNN_FLAG_COUNTERS) {
+            unsigned long long w[5] = {0, 0, 0, 0, 0};
+            HIP_OR_FAIL(c, hipMemcpy(w, c->counters, sizeof w, hipMemcpyDeviceToHost));
+            out->wave_candidate_steps = (int64_t)w[0];
+            out->wave_merges = (int64_t)w[1];
+            out->wave_node_visits = (int64_t)w[2];
+            out->wave_leaf_sweeps = (int64_t)w[3];
+            out->wavefronts = (int64_t)w[4];
+        }
         out->leaves = c->n > 0 ? h.n_leaves : 0;
         out->nodes = c->n > 0 ? h.n_nodes : 0;
-        out->deepest_level = (int32_t)h.deepest_level;
+        out->deepest_level = (h.deepest >> 8) == c->build_epoch ? (int32_t)(h.deepest & 0xff) : 0;
         if ((c->cfg.flags & MKNN_FLAG_TIMING) && c->have_events) {
             float ms = 0;
             if (hipEventElapsedTime(&ms, c->ev[0], c->ev[1]) == hipSuccess) out->ms_build = ms;

@@ -105,92 +105,138 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *total)
 }
 
 // ---------------------------------------------------------------------------
-// Device-wide exclusive scan of uint32 (three launches)
+// Decoupled look-back: tile t publishes its aggregate, then walks back over
+// tiles t-1, t-2, ... adding aggregates until it meets an inclusive prefix,
+// and publishes its own inclusive prefix.  A word holds a 2-bit flag and a
+// 62-bit value, written and read as one 64-bit atomic.  Tiles take tickets
+// in the order they start, so a tile only ever waits on tiles that are
+// already running, and every tile publishes its aggregate before it waits:
+// the waits always end.  A bounded spin records an error instead of
+// hanging if that reasoning were ever violated.
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t *__restrict__ in,
-                                                             uint32_t n,
-                                                             uint32_t *__restrict__ sums,
-                                                             const uint32_t *__restrict__ n_dev)
+constexpr uint64_t kLbAgg = 1ull << 62;
+constexpr uint64_t kLbInc = 2ull << 62;
+constexpr uint64_t kLbVal = (1ull << 62) - 1;
+constexpr uint32_t kSpinLimit = 1u << 22;
+
+__device__ __forceinline__ void lb_store(uint64_t *w, uint64_t v)
 {
-    if (n_dev) n = min(n, *n_dev);
-    const uint32_t base = blockIdx.x * (uint32_t)kScanTile;
-    uint32_t s = 0;
-#pragma unroll
-    for (int j = 0; j < kScanItems; ++j) {
-        uint32_t p = base + j * kScanThreads + threadIdx.x;
-        s += (p < n) ? in[p] : 0u;
-    }
-    uint32_t total;
-    block_excl_scan<kScanThreads>(s, &total);
-    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+    __hip_atomic_store(w, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ __launch_bounds__(1024) void k_scan_top(uint32_t *__restrict__ sums, uint32_t nb,
-                                                  uint32_t *__restrict__ total_out)
+__device__ __forceinline__ uint64_t lb_load(uint64_t *w)
 {
-    uint32_t carry = 0;
-    for (uint32_t base = 0; base < nb; base += 1024u * 4u) {
-        uint32_t v[4], s = 0;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            uint32_t p = base + threadIdx.x * 4u + j;
-            v[j] = (p < nb) ? sums[p] : 0u;
-            s += v[j];
-        }
-        uint32_t tot;
-        uint32_t pre = block_excl_scan<1024>(s, &tot) + carry;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            uint32_t p = base + threadIdx.x * 4u + j;
-            if (p < nb) sums[p] = pre;
-            pre += v[j];
-        }
-        carry += tot;
-    }
-    if (threadIdx.x == 0 && total_out) *total_out = carry;
+    return __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t *in, uint32_t *out,
-                                                           uint32_t n,
-                                                           const uint32_t *__restrict__ sums,
-                                                           const uint32_t *__restrict__ n_dev)
+// Publish the tile's aggregate (tile 0 publishes it as its inclusive prefix).
+__device__ __forceinline__ void lb_publish(uint64_t *status, uint32_t stride, uint32_t tile,
+                                           uint64_t agg)
 {
+    lb_store(status + (uint64_t)tile * stride, (tile == 0 ? kLbInc : kLbAgg) | agg);
+}
+
+// Exclusive prefix of the tile, then publish the inclusive prefix.
+__device__ __forceinline__ uint64_t lb_resolve(uint64_t *status, uint32_t stride, uint32_t tile,
+                                               uint64_t agg, uint32_t *err)
+{
+    if (tile == 0) return 0;
+    uint64_t excl = 0;
+    int64_t t = (int64_t)tile - 1;
+    uint32_t spins = 0;
+    while (t >= 0) {
+        const uint64_t w = lb_load(status + (uint64_t)t * stride);
+        const uint64_t flag = w & ~kLbVal;
+        if (flag == 0) {
+            if (++spins > kSpinLimit) {
+                atomicOr(err, 1u);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        excl += w & kLbVal;
+        if (flag == kLbInc) break;
+        --t;
+    }
+    lb_store(status + (uint64_t)tile * stride, kLbInc | (excl + agg));
+    return excl;
+}
+
+__device__ __forceinline__ uint32_t take_ticket(uint32_t *ticket)
+{
+    __shared__ uint32_t s_ticket;
+    if (threadIdx.x == 0) s_ticket = atomicAdd(ticket, 1u);
+    __syncthreads();
+    return s_ticket;
+}
+
+// ---------------------------------------------------------------------------
+// Single-pass exclusive scan of uint32
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_lb(const uint32_t *in, uint32_t *out,
+                                                         uint32_t n,
+                                                         const uint32_t *__restrict__ n_dev,
+                                                         ScanSpace sp,
+                                                         uint32_t *__restrict__ total)
+{
+    __shared__ uint32_t s_excl;
     if (n_dev) n = min(n, *n_dev);
-    if (blockIdx.x * (uint32_t)kScanTile >= n) return;
+    const uint32_t tile = take_ticket(sp.ticket);
+    const uint32_t base = tile * (uint32_t)kScanTile;
+    if (base >= n && !(n == 0 && tile == 0)) return;  // past the data; nobody waits on it
     // Blocked arrangement: thread t owns kScanItems consecutive elements.
-    const uint32_t base = blockIdx.x * (uint32_t)kScanTile + threadIdx.x * (uint32_t)kScanItems;
-    uint32_t v[kScanItems], s = 0;
+    const uint32_t mine = base + threadIdx.x * (uint32_t)kScanItems;
+    uint32_t v[kScanItems], sum = 0;
 #pragma unroll
     for (int j = 0; j < kScanItems; ++j) {
-        uint32_t p = base + j;
+        const uint32_t p = mine + j;
         v[j] = (p < n) ? in[p] : 0u;
-        s += v[j];
+        sum += v[j];
     }
-    uint32_t pre = block_excl_scan<kScanThreads>(s, nullptr) + sums[blockIdx.x];
+    uint32_t agg;
+    uint32_t pre = block_excl_scan<kScanThreads>(sum, &agg);
+    if (threadIdx.x == 0) {
+        lb_publish(sp.status, 1, tile, agg);
+        const uint64_t e = lb_resolve(sp.status, 1, tile, agg, sp.err);
+        s_excl = (uint32_t)e;
+        if (total && base + kScanTile >= n) *total = (uint32_t)e + agg;
+    }
+    __syncthreads();
+    pre += s_excl;
 #pragma unroll
     for (int j = 0; j < kScanItems; ++j) {
-        uint32_t p = base + j;
+        const uint32_t p = mine + j;
         if (p < n) out[p] = pre;
         pre += v[j];
     }
 }
 
-int64_t scan_tmp_elems(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
+int64_t scan_tiles(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
 
-__global__ void k_store_zero(uint32_t *p) { *p = 0u; }
-
-void launch_exclusive_scan(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp,
+void launch_exclusive_scan(const uint32_t *in, uint32_t *out, int64_t n, const ScanSpace &sp,
                            uint32_t *total, hipStream_t s, const uint32_t *n_dev)
 {
-    if (n <= 0) {
-        if (total) k_store_zero<<<1, 1, 0, s>>>(total);
-        return;
-    }
-    uint32_t nb = (uint32_t)((n + kScanTile - 1) / kScanTile);
-    k_scan_reduce<<<nb, kScanThreads, 0, s>>>(in, (uint32_t)n, tmp, n_dev);
-    k_scan_top<<<1, 1024, 0, s>>>(tmp, nb, total);
-    k_scan_down<<<nb, kScanThreads, 0, s>>>(in, out, (uint32_t)n, tmp, n_dev);
+    // At least one tile, so *total is written even for n = 0.
+    const uint32_t nb = (uint32_t)(n > 0 ? (n + kScanTile - 1) / kScanTile : 1);
+    k_scan_lb<<<nb, kScanThreads, 0, s>>>(in, out, (uint32_t)(n > 0 ? n : 0), n_dev, sp, total);
+}
+
+__global__ void k_zero_words(uint64_t *__restrict__ p, int64_t words)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0ull;
+}
+
+void launch_zero_words(uint64_t *p, int64_t words, hipStream_t s)
+{
+    if (words <= 0) return;
+    int64_t blocks = (words + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    k_zero_words<<<(uint32_t)blocks, 256, 0, s>>>(p, words);
 }
 
 // ---------------------------------------------------------------------------
@@ -199,14 +245,17 @@ void launch_exclusive_scan(const uint32_t *in, uint32_t *out, int64_t n, uint32_
 
 __global__ void k_morton(const float *__restrict__ x, const float *__restrict__ y, uint32_t n,
                          uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
-                         IndexCounters *__restrict__ ctr)
+                         IndexCounters *__restrict__ ctr, uint64_t *__restrict__ ws,
+                         int64_t ws_words, uint32_t epoch)
 {
-    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    // The build's scan and sort workspace starts at zero.
+    for (int64_t w = i; w < ws_words; w += (int64_t)gridDim.x * blockDim.x) ws[w] = 0ull;
     if (i >= n) return;
     float px = x[i], py = y[i];
     // NaN fails both comparisons; -0.0 passes.
     bool ok = (px >= 0.0f) && (px < 1.0f) && (py >= 0.0f) && (py < 1.0f);
-    if (!ok) atomicOr(&ctr->bad_input, 1u);
+    if (!ok) atomicMax(&ctr->bad_coord, epoch);
     // Scaling by 2^16 is exact; truncation is the floor for x >= 0.  The
     // clamp only matters for rejected input.
     uint32_t cx = ok ? (uint32_t)(px * 65536.0f) : 0u;
@@ -218,46 +267,62 @@ __global__ void k_morton(const float *__restrict__ x, const float *__restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// Stable LSD radix sort, 8-bit digits
+// Stable LSD radix sort, 8-bit digits, one launch per pass
+//
+// k_radix_ghist counts every pass's digits over all keys in one read (keys
+// do not change between passes, only their order).  Each pass then runs one
+// kernel: a tile ranks its keys stably in LDS (rounds of 256 keys in
+// position order; within a wavefront, lanes holding the same digit are
+// found with ballots), publishes its per-digit counts, reorders the tile by
+// digit in LDS, finds each digit's offset among earlier tiles by
+// decoupled look-back (one thread per digit) and writes the tile out in
+// contiguous digit runs.
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t *__restrict__ keys,
-                                                            uint32_t n, int shift,
-                                                            uint32_t *__restrict__ hist,
-                                                            uint32_t ntiles)
+constexpr int kGhistItems = 32;  // keys per thread in the histogram kernel
+
+__global__ __launch_bounds__(kSortThreads) void k_radix_ghist(const uint32_t *__restrict__ keys,
+                                                             uint32_t n, int passes,
+                                                             uint32_t *__restrict__ ghist)
 {
-    __shared__ uint32_t s_h[kRadixBins];
-    s_h[threadIdx.x] = 0;
-    __syncthreads();
-    const uint32_t base = blockIdx.x * (uint32_t)kSortTile;
+    __shared__ uint32_t s_h[kMaxRadixPasses][kRadixBins];
 #pragma unroll
-    for (int j = 0; j < kSortItems; ++j) {
-        uint32_t p = base + j * kSortThreads + threadIdx.x;
-        if (p < n) atomicAdd(&s_h[(keys[p] >> shift) & (kRadixBins - 1)], 1u);
+    for (int p = 0; p < kMaxRadixPasses; ++p) s_h[p][threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t base = blockIdx.x * (uint32_t)(kSortThreads * kGhistItems);
+    for (int j = 0; j < kGhistItems; ++j) {
+        const uint32_t i = base + j * kSortThreads + threadIdx.x;
+        if (i < n) {
+            const uint32_t k = keys[i];
+            for (int p = 0; p < passes; ++p)
+                atomicAdd(&s_h[p][(k >> (kRadixBits * p)) & (kRadixBins - 1)], 1u);
+        }
     }
     __syncthreads();
-    hist[threadIdx.x * ntiles + blockIdx.x] = s_h[threadIdx.x];
+    for (int p = 0; p < passes; ++p) {
+        const uint32_t c = s_h[p][threadIdx.x];
+        if (c) atomicAdd(&ghist[p * kRadixBins + threadIdx.x], c);
+    }
 }
 
-// Each tile is ranked stably in LDS (rounds of 256 keys in position order;
-// within a wavefront, lanes holding the same digit are found with ballots),
-// reordered by digit in LDS, then written to its global digit offsets in
-// contiguous runs.
-__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
+__global__ __launch_bounds__(kSortThreads) void k_radix_pass(
     const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ vals_in,
     uint32_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out, uint32_t n, int shift,
-    const uint32_t *__restrict__ offs, uint32_t ntiles)
+    const uint32_t *__restrict__ ghist, uint64_t *__restrict__ status, uint32_t *__restrict__ ticket,
+    uint32_t *__restrict__ err)
 {
     constexpr int NW = kSortThreads / kWave;
     __shared__ uint32_t s_keys[kSortTile];
     __shared__ uint32_t s_vals[kSortTile];
     __shared__ uint32_t s_start[kRadixBins];
     __shared__ uint32_t s_run[kRadixBins];
+    __shared__ uint32_t s_base[kRadixBins];
     __shared__ uint32_t s_wcnt[NW][kRadixBins];
     __shared__ uint32_t s_wbase[NW][kRadixBins];
 
     const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
-    const uint32_t base = blockIdx.x * (uint32_t)kSortTile;
+    const uint32_t tile = take_ticket(ticket);
+    const uint32_t base = tile * (uint32_t)kSortTile;
     const uint32_t n_valid = min((uint32_t)kSortTile, n - base);
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
 
@@ -265,8 +330,8 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     int dig[kSortItems];
 #pragma unroll
     for (int j = 0; j < kSortItems; ++j) {
-        uint32_t p = j * kSortThreads + t;
-        bool v = p < n_valid;
+        const uint32_t p = j * kSortThreads + t;
+        const bool v = p < n_valid;
         key[j] = v ? keys_in[base + p] : 0xffffffffu;
         val[j] = v ? vals_in[base + p] : 0u;
         // Padding takes the last digit; it sits at the end of the tile's
@@ -280,7 +345,11 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
 #pragma unroll
     for (int j = 0; j < kSortItems; ++j) atomicAdd(&s_start[dig[j]], 1u);
     __syncthreads();
-    uint32_t cnt = s_start[t];
+    const uint32_t cnt = s_start[t];
+    // Publish this tile's count of digit t (padding excluded) right away, so
+    // later tiles can resolve while this one ranks.
+    const uint32_t real = cnt - (t == kRadixBins - 1 ? (uint32_t)kSortTile - n_valid : 0u);
+    lb_publish(status + t, kRadixBins, tile, real);
     __syncthreads();
     s_start[t] = block_excl_scan<kSortThreads>(cnt, nullptr);
 
@@ -290,7 +359,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
         uint64_t peers = ~0ull;
 #pragma unroll
         for (int b = 0; b < kRadixBits; ++b) {
-            uint64_t m = __ballot((d >> b) & 1);
+            const uint64_t m = __ballot((d >> b) & 1);
             peers &= ((d >> b) & 1) ? m : ~m;
         }
         const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
@@ -313,42 +382,76 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
         s_keys[local] = key[j];
         s_vals[local] = val[j];
     }
+
+    // Offset of digit t: keys of smaller digits anywhere, plus keys of digit
+    // t in earlier tiles.
+    {
+        uint32_t below;
+        const uint32_t g = ghist[t];
+        below = block_excl_scan<kSortThreads>(g, nullptr);
+        const uint64_t before = lb_resolve(status + t, kRadixBins, tile, real, err);
+        s_base[t] = below + (uint32_t)before;
+    }
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < kSortItems; ++j) {
-        uint32_t lp = j * kSortThreads + t;
+        const uint32_t lp = j * kSortThreads + t;
         if (lp < n_valid) {
-            uint32_t k = s_keys[lp];
-            uint32_t d = (k >> shift) & (kRadixBins - 1);
-            uint32_t dst = offs[d * ntiles + blockIdx.x] + (lp - s_start[d]);
+            const uint32_t k = s_keys[lp];
+            const uint32_t d = (k >> shift) & (kRadixBins - 1);
+            const uint32_t dst = s_base[d] + (lp - s_start[d]);
             keys_out[dst] = k;
             vals_out[dst] = s_vals[lp];
         }
     }
 }
 
-int64_t radix_hist_elems(int64_t n)
-{
-    int64_t tiles = (n + kSortTile - 1) / kSortTile;
-    return (tiles > 0 ? tiles : 1) * kRadixBins;
-}
+int64_t radix_tiles(int64_t n) { return n > 0 ? (n + kSortTile - 1) / kSortTile : 1; }
 
 int launch_radix_sort(const SortBuffers &b, int64_t n, int bits, hipStream_t s)
 {
     int cur = 0;
     if (n <= 1) return cur;
-    const uint32_t ntiles = (uint32_t)((n + kSortTile - 1) / kSortTile);
-    const int64_t nh = (int64_t)ntiles * kRadixBins;
-    for (int shift = 0; shift < bits; shift += kRadixBits) {
-        k_radix_hist<<<ntiles, kSortThreads, 0, s>>>(b.keys[cur], (uint32_t)n, shift, b.hist,
-                                                     ntiles);
-        launch_exclusive_scan(b.hist, b.hist, nh, b.scan_tmp, nullptr, s);
-        k_radix_scatter<<<ntiles, kSortThreads, 0, s>>>(b.keys[cur], b.vals[cur],
-                                                        b.keys[cur ^ 1], b.vals[cur ^ 1],
-                                                        (uint32_t)n, shift, b.hist, ntiles);
+    const uint32_t ntiles = (uint32_t)radix_tiles(n);
+    const int passes = (bits + kRadixBits - 1) / kRadixBits;
+    const uint32_t gblocks = (uint32_t)((n + kSortThreads * kGhistItems - 1) / (kSortThreads * kGhistItems));
+    k_radix_ghist<<<gblocks, kSortThreads, 0, s>>>(b.keys[0], (uint32_t)n, passes, b.ghist);
+    for (int p = 0; p < passes; ++p) {
+        k_radix_pass<<<ntiles, kSortThreads, 0, s>>>(
+            b.keys[cur], b.vals[cur], b.keys[cur ^ 1], b.vals[cur ^ 1], (uint32_t)n,
+            kRadixBits * p, b.ghist + p * kRadixBins,
+            b.status + (uint64_t)p * ntiles * kRadixBins, b.tickets + p, b.err);
         cur ^= 1;
     }
     return cur;
+}
+
+int64_t workspace_words(int64_t n)
+{
+    // ghist (u32) + tickets + err, then radix look-back words, then scans.
+    const int64_t small = (kMaxRadixPasses * kRadixBins + 16 + 8) / 2 + 8;
+    return small + (int64_t)kMaxRadixPasses * radix_tiles(n) * kRadixBins + 4 * scan_tiles(n) + 16;
+}
+
+int64_t carve_workspace(const Workspace &ws, int64_t n, SortBuffers *sort, ScanSpace *scans,
+                        int n_scans)
+{
+    uint64_t *p = ws.base;
+    uint32_t *small = (uint32_t *)p;
+    sort->ghist = small;                                   // [4][256]
+    sort->tickets = small + kMaxRadixPasses * kRadixBins;  // [4]
+    sort->err = sort->tickets + kMaxRadixPasses;           // [1]
+    uint32_t *scan_tickets = sort->err + 1;                // [n_scans]
+    p += (kMaxRadixPasses * kRadixBins + 16 + 8) / 2 + 8;
+    sort->status = p;
+    p += (int64_t)kMaxRadixPasses * radix_tiles(n) * kRadixBins;
+    for (int i = 0; i < n_scans; ++i) {
+        scans[i].status = p;
+        scans[i].ticket = scan_tickets + i;
+        scans[i].err = sort->err;
+        p += scan_tiles(n);
+    }
+    return (int64_t)(p - ws.base);
 }
 
 // ---------------------------------------------------------------------------
@@ -357,7 +460,7 @@ int launch_radix_sort(const SortBuffers &b, int64_t n, int bits, hipStream_t s)
 
 __global__ void k_gather(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ vals,
                          const float *__restrict__ x, const float *__restrict__ y, uint32_t n,
-                         Point *__restrict__ pts, int32_t *__restrict__ inv)
+                         Point *__restrict__ pts)
 {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -368,7 +471,19 @@ __global__ void k_gather(const uint32_t *__restrict__ keys, const uint32_t *__re
     p.id = id;
     p.code = keys[i];
     pts[i] = p;
-    inv[id] = (int32_t)i;
+}
+
+// Sorted position of every object id; only subset queries need it.
+__global__ void k_inverse(const Point *__restrict__ pts, uint32_t n, int32_t *__restrict__ inv)
+{
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) inv[pts[i].id] = (int32_t)i;
+}
+
+void launch_inverse(const IndexBuffers &b, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return;
+    k_inverse<<<(uint32_t)((n + 255) / 256), 256, 0, s>>>(b.pts, (uint32_t)n, b.inv);
 }
 
 // flags[0] = 1; flags[i+1] = 1 iff sorted objects i and i+1 lie in different
@@ -432,28 +547,34 @@ __global__ void k_leaf_emit(const uint32_t *__restrict__ flags, const uint32_t *
 __global__ void k_leaf_info(const uint32_t *__restrict__ codes, uint32_t n, int th, int L,
                             const int32_t *__restrict__ leaf_begin,
                             const int32_t *__restrict__ leaf_end, IndexCounters *__restrict__ ctr,
-                            int32_t *__restrict__ leaf_level, uint32_t *__restrict__ cnt_f,
-                            uint32_t *__restrict__ cnt_r)
+                            int32_t *__restrict__ leaf_level, uint32_t *__restrict__ leaf_code,
+                            uint32_t *__restrict__ cnt_f, uint32_t *__restrict__ cnt_r,
+                            uint32_t epoch)
 {
+    // Grid-stride over the leaves (their count is only known on the device).
     const uint32_t nl = ctr->n_leaves;
-    const uint32_t j0 = blockIdx.x * blockDim.x;
-    if (j0 >= nl) return;  // whole block past the last leaf
-    const uint32_t j = j0 + threadIdx.x;
-    int lev = 0;
-    if (j < nl) {
-        const int32_t b = leaf_begin[j], e = leaf_end[j];
-        const int cl = b > 0 ? common_level(codes[b - 1], codes[b]) : -1;
-        const int cr = (uint32_t)e < n ? common_level(codes[e - 1], codes[e]) : -1;
-        lev = (e - b <= th) ? max(cl, cr) + 1 : L;
-        leaf_level[j] = lev;
-        cnt_f[j] = (uint32_t)(lev - cl);
-        cnt_r[j] = (uint32_t)(lev - cr);
+    const uint32_t stride = gridDim.x * blockDim.x;
+    int deepest = 0;
+    for (uint32_t j0 = blockIdx.x * blockDim.x; j0 < nl; j0 += stride) {
+        const uint32_t j = j0 + threadIdx.x;
+        if (j < nl) {
+            const int32_t b = leaf_begin[j], e = leaf_end[j];
+            const int cl = b > 0 ? common_level(codes[b - 1], codes[b]) : -1;
+            const int cr = (uint32_t)e < n ? common_level(codes[e - 1], codes[e]) : -1;
+            const int lev = (e - b <= th) ? max(cl, cr) + 1 : L;
+            leaf_level[j] = lev;
+            leaf_code[j] = codes[b];
+            cnt_f[j] = (uint32_t)(lev - cl);
+            cnt_r[j] = (uint32_t)(lev - cr);
+            deepest = max(deepest, lev);
+        }
     }
-    // Statistic only: one atomic per wavefront that holds leaves.
-    int deepest = lev;
+    // Statistic only: one atomic per wavefront that saw leaves.
 #pragma unroll
     for (int d = 1; d < kWave; d <<= 1) deepest = max(deepest, __shfl_xor(deepest, d, kWave));
-    if ((threadIdx.x & (kWave - 1)) == 0 && j < nl) atomicMax(&ctr->deepest_level, (uint32_t)deepest);
+    const uint32_t wave0 = blockIdx.x * blockDim.x + (threadIdx.x & ~(kWave - 1));
+    if ((threadIdx.x & (kWave - 1)) == 0 && wave0 < nl)
+        atomicMax(&ctr->deepest, (epoch << 8) | (uint32_t)deepest);
 }
 
 __device__ __forceinline__ void node_box(uint32_t code, int l, Node &nd)
@@ -468,106 +589,142 @@ __device__ __forceinline__ void node_box(uint32_t code, int l, Node &nd)
     nd.y1 = (float)(cy + side) * s;
 }
 
-// One work item per (leaf j, slot s): slot s of leaf j's forward nodes is
-// its ancestor at level cl+1+s (the leaf itself for the last slot), slot s
-// of its backward nodes the ancestor at level cr+1+s.  Inner nodes find the
-// end of their subtree by a binary search over the leaves' first codes.
+// One thread per leaf j emits its forward nodes (its ancestors below the
+// deepest quadrant shared with leaf j-1, then itself) and its backward
+// nodes (likewise with leaf j+1).  An inner node's subtree ends where the
+// leaves' first codes leave its quadrant; that boundary is found by a
+// galloping search over the leaf codes (subtrees are mostly small), the
+// forward and backward searches of a level running together.
+__device__ __forceinline__ uint32_t gallop_up(const uint32_t *__restrict__ lc, uint32_t j,
+                                              uint32_t nl, uint32_t code, int l)
+{
+    // First leaf index > j whose code leaves the level-l quadrant of code.
+    uint32_t lo = j, step = 1, hi;
+    for (;;) {
+        const uint32_t p = j + step;
+        if (p >= nl) { hi = nl; break; }
+        if (!same_quadrant(lc[p], code, l)) { hi = p; break; }
+        lo = p;
+        step <<= 1;
+    }
+    ++lo;  // lo: first candidate not yet known inside
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (same_quadrant(lc[mid], code, l)) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ uint32_t gallop_down(const uint32_t *__restrict__ lc, uint32_t j,
+                                                uint32_t code, int l)
+{
+    // Lowest leaf index <= j whose code lies in the level-l quadrant of code.
+    uint32_t hi = j, step = 1, lo;
+    for (;;) {
+        if (step > j) { lo = 0; break; }
+        const uint32_t p = j - step;
+        if (!same_quadrant(lc[p], code, l)) { lo = p + 1; break; }
+        hi = p;
+        step <<= 1;
+    }
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (same_quadrant(lc[mid], code, l)) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
+// The nodes leaf j contributes to both tables.
+__device__ void emit_leaf_nodes(const uint32_t *__restrict__ codes, uint32_t n,
+                                const int32_t *__restrict__ leaf_begin,
+                                const int32_t *__restrict__ leaf_end,
+                                const int32_t *__restrict__ leaf_level,
+                                const uint32_t *__restrict__ leaf_code,
+                                const uint32_t *__restrict__ off_f,
+                                const uint32_t *__restrict__ off_r, uint32_t nl, uint32_t total,
+                                Node *__restrict__ fwd, Node *__restrict__ rev,
+                                int32_t *__restrict__ leaf_node_f,
+                                int32_t *__restrict__ leaf_node_r, uint32_t node_cap, uint32_t j)
+{
+    const int32_t b = leaf_begin[j], e = leaf_end[j];
+    const int lev = leaf_level[j];
+    const uint32_t code = leaf_code[j];
+    const int cl = b > 0 ? common_level(codes[b - 1], code) : -1;
+    const int cr = (uint32_t)e < n ? common_level(codes[e - 1], codes[e]) : -1;
+    const uint32_t fbase = off_f[j];
+    // Backward table: nodes of all later leaves come first.
+    const uint32_t rbase = total - off_r[j] - (uint32_t)(lev - cr);
+
+    for (int l = min(cl, cr) + 1; l <= lev; ++l) {
+        const bool do_f = l > cl, do_r = l > cr;
+        Node nd;
+        node_box(code, l, nd);
+        if (l == lev) {
+            nd.begin = b;
+            nd.end = e;
+            nd.leaf = (int32_t)j;
+            const uint32_t fi = fbase + (uint32_t)(l - cl - 1);
+            const uint32_t ri = rbase + (uint32_t)(l - cr - 1);
+            nd.skip = (int32_t)fi + 1;
+            if (fi < node_cap) fwd[fi] = nd;
+            leaf_node_f[j] = (int32_t)fi;
+            nd.skip = (int32_t)ri + 1;
+            if (ri < node_cap) rev[ri] = nd;
+            leaf_node_r[j] = (int32_t)ri;
+            break;
+        }
+        nd.leaf = -1;
+        if (do_f) {
+            const uint32_t hi = gallop_up(leaf_code, j, nl, code, l);
+            const uint32_t fi = fbase + (uint32_t)(l - cl - 1);
+            nd.begin = b;
+            nd.end = hi < nl ? leaf_begin[hi] : (int32_t)n;
+            nd.skip = hi < nl ? (int32_t)off_f[hi] : (int32_t)total;
+            if (fi < node_cap) fwd[fi] = nd;
+        }
+        if (do_r) {
+            const uint32_t lo = gallop_down(leaf_code, j, code, l);
+            const uint32_t ri = rbase + (uint32_t)(l - cr - 1);
+            nd.begin = leaf_begin[lo];
+            nd.end = e;
+            if (lo > 0) {
+                const int32_t pe = leaf_end[lo - 1];
+                const int pcr = common_level(codes[pe - 1], codes[pe]);
+                nd.skip = (int32_t)(total - off_r[lo - 1] - (uint32_t)(leaf_level[lo - 1] - pcr));
+            } else {
+                nd.skip = (int32_t)total;
+            }
+            if (ri < node_cap) rev[ri] = nd;
+        }
+    }
+}
+
 __global__ void k_node_emit(const uint32_t *__restrict__ codes, uint32_t n,
                             const int32_t *__restrict__ leaf_begin,
                             const int32_t *__restrict__ leaf_end,
                             const int32_t *__restrict__ leaf_level,
+                            const uint32_t *__restrict__ leaf_code,
                             const uint32_t *__restrict__ off_f, const uint32_t *__restrict__ off_r,
                             IndexCounters *__restrict__ ctr, Node *__restrict__ fwd,
                             Node *__restrict__ rev, int32_t *__restrict__ leaf_node_f,
-                            int32_t *__restrict__ leaf_node_r, uint32_t node_cap)
+                            int32_t *__restrict__ leaf_node_r, uint32_t node_cap,
+                            uint32_t epoch)
 {
-    constexpr uint32_t kSlots = kCodeLevels + 1;
     const uint32_t nl = ctr->n_leaves;
     const uint32_t total = ctr->n_nodes;
     if (total > node_cap) {
         // Cannot happen for a correct build (the capacity bounds the tree);
         // refuse to write rather than overrun.
-        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&ctr->bad_input, 8u);
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicMax(&ctr->bad_nodes, epoch);
         return;
     }
-    const uint64_t items = (uint64_t)nl * kSlots;
-    for (uint64_t it = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; it < items;
-         it += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t j = (uint32_t)(it / kSlots);
-        const int sl = (int)(it % kSlots);
-        const int32_t b = leaf_begin[j], e = leaf_end[j];
-        const int lev = leaf_level[j];
-        const uint32_t code = codes[b];
-        const int cl = b > 0 ? common_level(codes[b - 1], codes[b]) : -1;
-        const int cr = (uint32_t)e < n ? common_level(codes[e - 1], codes[e]) : -1;
-
-        const int lf = cl + 1 + sl;  // forward level of this slot
-        if (lf <= lev) {
-            Node nd;
-            node_box(code, lf, nd);
-            const uint32_t idx = off_f[j] + (uint32_t)sl;
-            if (lf == lev) {
-                nd.begin = b;
-                nd.end = e;
-                nd.skip = (int32_t)idx + 1;
-                nd.leaf = (int32_t)j;
-                leaf_node_f[j] = (int32_t)idx;
-            } else {
-                // First later leaf outside this quadrant.
-                uint32_t lo = j + 1, hi = nl;
-                while (lo < hi) {
-                    const uint32_t mid = (lo + hi) >> 1;
-                    if (same_quadrant(codes[leaf_begin[mid]], code, lf)) lo = mid + 1;
-                    else hi = mid;
-                }
-                nd.begin = b;
-                nd.end = lo < nl ? leaf_begin[lo] : (int32_t)n;
-                nd.skip = lo < nl ? (int32_t)off_f[lo] : (int32_t)total;
-                nd.leaf = -1;
-            }
-            if (idx < node_cap) fwd[idx] = nd;
-        }
-        const int lr = cr + 1 + sl;  // backward level of this slot
-        if (lr <= lev) {
-            Node nd;
-            node_box(code, lr, nd);
-            // Backward table: nodes of all later leaves come first.
-            const uint32_t rbase = total - off_r[j] - (uint32_t)(lev - cr);
-            const uint32_t idx = rbase + (uint32_t)sl;
-            if (lr == lev) {
-                nd.begin = b;
-                nd.end = e;
-                nd.skip = (int32_t)idx + 1;
-                nd.leaf = (int32_t)j;
-                leaf_node_r[j] = (int32_t)idx;
-            } else {
-                // First (lowest) leaf inside this quadrant.
-                uint32_t lo = 0, hi = j;
-                while (lo < hi) {
-                    const uint32_t mid = (lo + hi) >> 1;
-                    if (same_quadrant(codes[leaf_begin[mid]], code, lr)) hi = mid;
-                    else lo = mid + 1;
-                }
-                nd.begin = leaf_begin[lo];
-                nd.end = e;
-                if (lo > 0) {
-                    const int32_t pe = leaf_end[lo - 1];
-                    const int pcr = common_level(codes[pe - 1], codes[pe]);
-                    nd.skip = (int32_t)(total - off_r[lo - 1] - (uint32_t)(leaf_level[lo - 1] - pcr));
-                } else {
-                    nd.skip = (int32_t)total;
-                }
-                nd.leaf = -1;
-            }
-            if (idx < node_cap) rev[idx] = nd;
-        }
-    }
+    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < nl; j += gridDim.x * blockDim.x)
+        emit_leaf_nodes(codes, n, leaf_begin, leaf_end, leaf_level, leaf_code, off_f, off_r, nl,
+                        total, fwd, rev, leaf_node_f, leaf_node_r, node_cap, j);
 }
 
-__global__ void k_set_leaf_count(IndexCounters *ctr, const uint32_t *flags_total)
-{
-    ctr->n_leaves = *flags_total;
-}
 
 int64_t node_capacity(int64_t n, int th, int L)
 {
@@ -580,30 +737,33 @@ int64_t node_capacity(int64_t n, int th, int L)
 }
 
 void launch_build_index(IndexBuffers &b, const float *x, const float *y, int64_t n, int th,
-                        int L, hipStream_t s)
+                        int L, uint32_t epoch, hipStream_t s)
 {
     const uint32_t nn = (uint32_t)n;
     const int T = 256;
     const uint32_t g = (uint32_t)((n + T - 1) / T);
     if (n == 0) return;
-    k_morton<<<g, T, 0, s>>>(x, y, nn, b.sort.keys[0], b.sort.vals[0], b.ctr);
+    const int64_t words = carve_workspace(b.ws, n, &b.sort, b.scan, 3);
+    k_morton<<<g, T, 0, s>>>(x, y, nn, b.sort.keys[0], b.sort.vals[0], b.ctr, b.ws.base, words,
+                             epoch);
     const int res = launch_radix_sort(b.sort, n, 2 * kCodeLevels, s);
     const uint32_t *codes = b.sort.keys[res];
-    k_gather<<<g, T, 0, s>>>(codes, b.sort.vals[res], x, y, nn, b.pts, b.inv);
+    k_gather<<<g, T, 0, s>>>(codes, b.sort.vals[res], x, y, nn, b.pts);
     k_leaf_flags<<<g, T, 0, s>>>(codes, nn, th, L, b.flags);
-    // The exclusive scan goes to the other key buffer; its sum is the leaf
+    // The exclusive scan goes to the other value buffer; its sum is the leaf
     // count.
     uint32_t *excl = b.sort.vals[res ^ 1];
-    launch_exclusive_scan(b.flags, excl, n, b.sort.scan_tmp, &b.ctr->n_leaves, s);
+    launch_exclusive_scan(b.flags, excl, n, b.scan[0], &b.ctr->n_leaves, s);
     k_leaf_emit<<<g, T, 0, s>>>(b.flags, excl, nn, b.leaf_of, b.leaf_begin, b.leaf_end);
-    k_leaf_info<<<g, T, 0, s>>>(codes, nn, th, L, b.leaf_begin, b.leaf_end, b.ctr, b.leaf_level,
-                                b.cnt_f, b.cnt_r);
-    launch_exclusive_scan(b.cnt_f, b.cnt_f, n, b.sort.scan_tmp, &b.ctr->n_nodes, s,
-                          &b.ctr->n_leaves);
-    launch_exclusive_scan(b.cnt_r, b.cnt_r, n, b.sort.scan_tmp, nullptr, s, &b.ctr->n_leaves);
-    k_node_emit<<<1024, T, 0, s>>>(codes, nn, b.leaf_begin, b.leaf_end, b.leaf_level, b.cnt_f,
-                                b.cnt_r, b.ctr, b.fwd, b.rev, b.leaf_node_f, b.leaf_node_r,
-                                (uint32_t)b.node_cap);
+    // Leaf-bounded kernels: a fixed grid striding over the device-side count.
+    const uint32_t gl = g < 512 ? g : 512;
+    k_leaf_info<<<gl, T, 0, s>>>(codes, nn, th, L, b.leaf_begin, b.leaf_end, b.ctr, b.leaf_level,
+                                b.leaf_code, b.cnt_f, b.cnt_r, epoch);
+    launch_exclusive_scan(b.cnt_f, b.cnt_f, n, b.scan[1], &b.ctr->n_nodes, s, &b.ctr->n_leaves);
+    launch_exclusive_scan(b.cnt_r, b.cnt_r, n, b.scan[2], nullptr, s, &b.ctr->n_leaves);
+    k_node_emit<<<gl, T, 0, s>>>(codes, nn, b.leaf_begin, b.leaf_end, b.leaf_level, b.leaf_code,
+                                b.cnt_f, b.cnt_r, b.ctr, b.fwd, b.rev, b.leaf_node_f,
+                                b.leaf_node_r, (uint32_t)b.node_cap, epoch);
 }
 
 }  // namespace mknn

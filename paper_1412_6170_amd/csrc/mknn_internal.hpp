@@ -39,20 +39,46 @@ struct __align__(16) Node {
 };
 
 // Device scalars written by the build and read by later kernels (no host
-// round trip between the build and the queries).
+// round trip between the build and the queries).  Flags and the deepest
+// level are tagged with the build's (or query's) epoch in their high bits
+// and raised with atomicMax, so nothing has to clear them between ticks:
+// a value from an older epoch is simply smaller.
 struct IndexCounters {
     uint32_t n_leaves;
     uint32_t n_nodes;
-    uint32_t deepest_level;
-    uint32_t bad_input;     // set when a coordinate is outside [0,1)
+    uint32_t deepest;        // (build epoch << 8) | deepest leaf level
+    uint32_t bad_coord;      // build epoch in which a coordinate was outside [0,1)
+    uint32_t bad_nodes;      // build epoch in which the node tables overflowed
+    uint32_t bad_issuer;     // query epoch in which an issuer was outside [0,n)
+    uint32_t bad_k;          // query epoch in which a k was outside [1,k_max]
+    uint32_t pad;
 };
 
-// Ping-pong buffers of a radix sort of (key, val) pairs.
+// Workspace of single-pass scans and radix passes.  Each pass or scan
+// owns one look-back word per tile (and, for radix passes, per digit) and a
+// tile ticket; all of it must be zero when the pass is launched.  A build
+// carves its workspace from one block of words that its first kernel zeroes.
+struct ScanSpace {
+    uint64_t *status;   // look-back words, one per tile
+    uint32_t *ticket;   // tile ticket counter
+    uint32_t *err;      // set if a look-back wait ever gave up
+};
+
+// Ping-pong buffers of a radix sort of (key, val) pairs and its workspace.
+constexpr int kMaxRadixPasses = 4;
 struct SortBuffers {
     uint32_t *keys[2];
     uint32_t *vals[2];
-    uint32_t *hist;         // kRadixBins * tiles
-    uint32_t *scan_tmp;     // block sums for device-wide scans
+    uint32_t *ghist;    // [kMaxRadixPasses][kRadixBins] global digit counts (zeroed)
+    uint64_t *status;   // [passes][tiles][kRadixBins] look-back words (zeroed)
+    uint32_t *tickets;  // [kMaxRadixPasses] tile tickets (zeroed)
+    uint32_t *err;
+};
+
+// A block of workspace words and how a build or a query carves it.
+struct Workspace {
+    uint64_t *base;
+    int64_t cap_words;
 };
 
 // Device memory of one context's index.  Sizes are capacities.
@@ -60,38 +86,59 @@ struct IndexBuffers {
     SortBuffers sort;
     // sorted objects
     Point *pts;
-    int32_t *inv;           // sorted position of each object id
+    int32_t *inv;           // sorted position of each object id (built on demand)
     int32_t *leaf_of;       // leaf index of each sorted position
     // leaves
     uint32_t *flags;        // leaf-start flags -> exclusive scan
     int32_t *leaf_begin, *leaf_end;
     int32_t *leaf_level;
+    uint32_t *leaf_code;       // code of each leaf's first object
     uint32_t *cnt_f, *cnt_r;   // nodes emitted per leaf -> offsets
     int32_t *leaf_node_f, *leaf_node_r;
     Node *fwd, *rev;
     IndexCounters *ctr;
-    int64_t n_cap, node_cap, hist_cap, scan_tmp_cap;
+    Workspace ws;
+    ScanSpace scan[3];         // flags, forward and backward node counts
+    int64_t n_cap, node_cap;
 };
 
 // Host launchers -------------------------------------------------------------
 
-// Scratch element counts needed for a device-wide exclusive scan of n items.
-int64_t scan_tmp_elems(int64_t n);
-// Exclusive scan of n uint32 values (in -> out may alias); *total, if not
-// null, receives the sum on the device.
-// If n_dev is given, only the first min(n, *n_dev) entries are scanned.
-void launch_exclusive_scan(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp,
+// Tiles of a single-pass scan over n items.
+int64_t scan_tiles(int64_t n);
+// Radix sort tiles for n keys.
+int64_t radix_tiles(int64_t n);
+// Workspace words a build over n objects (or a query sort of n keys plus a
+// scan of n values) needs.
+int64_t workspace_words(int64_t n);
+
+// Carve a sort workspace (n keys) and `scans` scan workspaces (n values
+// each) from ws; returns the number of words used.  The words must be
+// zeroed before the first pass runs.
+int64_t carve_workspace(const Workspace &ws, int64_t n, SortBuffers *sort, ScanSpace *scans,
+                        int n_scans);
+
+// Zero the first `words` words of a workspace.
+void launch_zero_words(uint64_t *p, int64_t words, hipStream_t s);
+
+// Exclusive scan of n uint32 values in one launch (in -> out may alias);
+// *total, if not null, receives the sum.  If n_dev is given, only the first
+// min(n, *n_dev) entries are scanned.  sp must be zero (it is consumed).
+void launch_exclusive_scan(const uint32_t *in, uint32_t *out, int64_t n, const ScanSpace &sp,
                            uint32_t *total, hipStream_t s, const uint32_t *n_dev = nullptr);
 
-// Number of histogram entries a radix sort of n keys needs.
-int64_t radix_hist_elems(int64_t n);
-// Stable LSD radix sort of (key, val) pairs by key bits [0, bits); the result
-// ends in keys[res], vals[res] where res is returned (0 or 1).
+// Stable LSD radix sort of (key, val) pairs by key bits [0, bits) (at most
+// 32); the result ends in keys[res], vals[res] where res is returned.  The
+// workspace in b must be zero (it is consumed).
 int launch_radix_sort(const SortBuffers &b, int64_t n, int bits, hipStream_t s);
 
-// Full index build over positions x, y (device, n objects).
+// Full index build over positions x, y (device, n objects); epoch tags the
+// build's flags (1 .. 2^24-1).
 void launch_build_index(IndexBuffers &b, const float *x, const float *y, int64_t n, int th,
-                        int max_level, hipStream_t s);
+                        int max_level, uint32_t epoch, hipStream_t s);
+
+// Sorted position of every object id (for subset queries).
+void launch_inverse(const IndexBuffers &b, int64_t n, hipStream_t s);
 
 // Node-table capacity needed for n objects, leaf capacity th, depth L.
 int64_t node_capacity(int64_t n, int th, int L);

@@ -38,7 +38,29 @@
 
 namespace mknn {
 
-constexpr uint64_t kKeyMax = ~0ull;
+// Keys are (d2 bits << 32 | id).  d2 is a non-negative finite float, so a
+// key is also the bit pattern of a non-negative finite double, and doubles
+// of that kind order exactly like their bit patterns (denormal doubles --
+// keys with d2 = 0 -- included, as the kernel keeps fp64 denormals).  The
+// selection networks therefore compare-exchange keys with one fp64 min and
+// one fp64 max.  The empty-slot key is the largest finite double, above
+// every real key (whose high word is at most 0x7f7fffff).
+constexpr uint64_t kKeyMax = 0x7fefffffffffffffull;
+
+__device__ __forceinline__ double as_f64(uint64_t k) { return __longlong_as_double((long long)k); }
+__device__ __forceinline__ uint64_t as_key(double d) { return (uint64_t)__double_as_longlong(d); }
+__device__ __forceinline__ uint64_t key_min(uint64_t a, uint64_t b)
+{
+    return as_key(__builtin_fmin(as_f64(a), as_f64(b)));
+}
+__device__ __forceinline__ uint64_t key_max(uint64_t a, uint64_t b)
+{
+    return as_key(__builtin_fmax(as_f64(a), as_f64(b)));
+}
+__device__ __forceinline__ bool key_less(uint64_t a, uint64_t b) { return as_f64(a) < as_f64(b); }
+
+// A 64-bit word in LDS (address space 3), so queue accesses stay ds_* ops.
+typedef __attribute__((address_space(3))) uint64_t lds_u64;
 
 __device__ __forceinline__ float sq_dist(float qx, float qy, float px, float py)
 {
@@ -63,9 +85,8 @@ __device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
 // Compare-exchange on keys: afterwards lo <= hi.
 __device__ __forceinline__ void cmp_swap(uint64_t &lo, uint64_t &hi)
 {
-    const bool s = lo > hi;
-    const uint64_t t = s ? hi : lo;
-    hi = s ? lo : hi;
+    const uint64_t t = key_min(lo, hi);
+    hi = key_max(lo, hi);
     lo = t;
 }
 
@@ -116,73 +137,114 @@ __device__ __forceinline__ void bitonic_merge(uint64_t (&a)[N])
 // a[]: the queue is sorted with a bitonic network, the lower K keys of
 // a[] and the queue are taken with one min against the reversed queue
 // (which leaves a bitonic sequence) and a bitonic merge sorts them.
-// The threshold is refreshed at each merge; between merges it may be
-// stale, which only lets more keys into the queue.
+//
+// The threshold is min(a[K-1], cap): cap is one above a key known not to be
+// exceeded by the k-th key (the k-th smallest key of any k other objects
+// bounds it from above), so filtering with it drops nothing that belongs to
+// the answer.  Between merges the threshold may be stale, which only lets
+// more keys into the queue.  The query's own object is queued like any
+// other candidate (its key is (0, own id)) and is removed at merge time.
 template <int K, int P>
 struct Selector {
     uint64_t a[K];
-    uint64_t *q;       // this lane's queue: q[s * kWave], s < P
+    lds_u64 *q;        // this lane's queue: q[s * kWave], s < P
     uint32_t cnt;
-    uint64_t thr;      // a[K-1] at the last merge
+    uint64_t cap;      // upper bound (exclusive) from the seed
+    uint64_t thr;      // min(a[K-1], cap) at the last merge
+    uint64_t self_key;
 
-    __device__ __forceinline__ void init(int k, uint64_t *lane_queue)
+    __device__ __forceinline__ void init(int k, lds_u64 *lane_queue, uint32_t self_id)
     {
 #pragma unroll
         for (int s = 0; s < K; ++s) a[s] = (s < K - k) ? 0ull : kKeyMax;
         q = lane_queue;
         cnt = 0;
+        cap = kKeyMax;
         thr = kKeyMax;
+        self_key = (uint64_t)self_id;  // d2 of the query to itself is +0
     }
 
-    __device__ __forceinline__ void push(uint64_t key)
+    __device__ __forceinline__ void set_cap(uint64_t c)
+    {
+        cap = c;
+        thr = key_min(a[K - 1], cap);
+    }
+
+    // Every lane writes its key to its next free slot; only lanes whose key
+    // passes advance.  No branch, so no lane waits on another's insertion.
+    __device__ __forceinline__ void offer(uint64_t key)
     {
         q[cnt * kWave] = key;
-        ++cnt;
+        cnt += key_less(key, thr) ? 1u : 0u;
     }
 
     __device__ __forceinline__ void merge()
     {
+        // Read every slot (volatile keeps the loads unconditional: slots
+        // past cnt hold stale keys and are masked after the load).
+        const volatile lds_u64 *vq = q;
         uint64_t b[P];
 #pragma unroll
-        for (int s = 0; s < P; ++s) b[s] = (uint32_t)s < cnt ? q[s * kWave] : kKeyMax;
+        for (int s = 0; s < P; ++s) b[s] = vq[s * kWave];
+#pragma unroll
+        for (int s = 0; s < P; ++s) b[s] = ((uint32_t)s < cnt && b[s] != self_key) ? b[s] : kKeyMax;
         bitonic_sort<P>(b);
 #pragma unroll
-        for (int i = K - P; i < K; ++i) a[i] = min(a[i], b[K - 1 - i]);
+        for (int i = K - P; i < K; ++i) a[i] = key_min(a[i], b[K - 1 - i]);
         bitonic_merge<K>(a);
         cnt = 0;
-        thr = a[K - 1];
+        thr = key_min(a[K - 1], cap);
     }
 };
 
 template <int K, int P>
 struct Lane {
     float qx, qy;
-    uint32_t self;
     bool active;
     Selector<K, P> sel;
+    uint32_t n_cand = 0, n_merge = 0, n_node = 0, n_leaf = 0;  // wave-uniform
 
-    __device__ __forceinline__ void consider(const Point &p)
+    __device__ __forceinline__ void offer(const Point &p)
     {
         const float d2 = sq_dist(qx, qy, p.x, p.y);
-        const uint32_t db = __float_as_uint(d2);
-        if (active && db <= (uint32_t)(sel.thr >> 32) && p.id != self) {
-            const uint64_t key = ((uint64_t)db << 32) | p.id;
-            if (key < sel.thr) sel.push(key);
+        sel.offer(((uint64_t)__float_as_uint(d2) << 32) | p.id);
+    }
+
+    __device__ __forceinline__ void merge_if(bool full)
+    {
+        if (wave_any(full)) {
+            sel.merge();
+            ++n_merge;
         }
-        if (wave_any(sel.cnt == (uint32_t)P)) sel.merge();
     }
 
     // Every lane evaluates every object of the sorted range [b, e).  The
-    // range is wave-uniform, so objects arrive through scalar loads; the
-    // next object is requested before the current one is used.
+    // range is wave-uniform, so objects arrive through scalar loads, two per
+    // step, with the next two requested before the current ones are used.
+    // Invariant between steps (and between sweeps): every queue holds at
+    // most P-2 keys, so a step's two writes stay inside the queue; a merge
+    // runs as soon as a queue holds more.
     __device__ __forceinline__ void sweep(const Point *__restrict__ pts, int32_t b, int32_t e)
     {
         if (b >= e) return;
-        Point c = pts[b];
-        for (int32_t j = b; j < e; ++j) {
-            const Point nx = pts[j + 1 < e ? j + 1 : j];
-            consider(c);
-            c = nx;
+        n_cand += (uint32_t)(e - b);
+        ++n_leaf;
+        int32_t j = b;
+        if (e - b >= 2) {
+            Point c0 = pts[j], c1 = pts[j + 1];
+            for (; j + 2 <= e; j += 2) {
+                const int32_t jn = j + 4 <= e ? j + 2 : j;
+                const Point n0 = pts[jn], n1 = pts[jn + 1];
+                offer(c0);
+                offer(c1);
+                merge_if(sel.cnt > (uint32_t)(P - 2));
+                c0 = n0;
+                c1 = n1;
+            }
+        }
+        if (j < e) {
+            offer(pts[j]);
+            merge_if(sel.cnt > (uint32_t)(P - 2));
         }
     }
 
@@ -206,6 +268,7 @@ __device__ __forceinline__ int32_t walk_step(Lane<K, P> &ln, const Node *__restr
 {
     while (pos < total) {
         const Node nd = tab[pos];
+        ++ln.n_node;
         const int32_t next = nd.skip > pos ? nd.skip : pos + 1;
         if (!wave_any(ln.wants(nd))) {
             pos = next;
@@ -237,11 +300,36 @@ __global__ __launch_bounds__(256) void k_knn_tiles(QueryArgs qa)
     const Point q = qa.pts[qp];
     ln.qx = q.x;
     ln.qy = q.y;
-    ln.self = q.id;
     const int32_t row = qa.qrow ? qa.qrow[tq] : (int32_t)q.id;
     int kq = qa.ks ? qa.ks[row] : qa.k_uniform;
     kq = kq < 1 ? 1 : (kq > K ? K : kq);
-    ln.sel.init(kq, &s_queue[wib][lane]);
+    ln.sel.init(kq, (lds_u64 *)&s_queue[wib][lane], q.id);
+
+    // Seed: the kq objects around the query in Morton order (a window of
+    // kq + 1 sorted positions holding the query) are kq other objects, so
+    // the largest of their keys bounds the k-th key from above.  Inactive
+    // lanes keep a zero threshold and never queue anything.
+    {
+        const int32_t n = (int32_t)qa.n;
+        uint64_t seed = 0;
+        if (n - 1 >= kq) {
+            int32_t w0 = qp - kq / 2;
+            w0 = w0 < 0 ? 0 : (w0 > n - 1 - kq ? n - 1 - kq : w0);
+#pragma unroll 4
+            for (int s = 0; s <= K; ++s) {
+                if (s <= kq) {
+                    const int32_t j = w0 + s;
+                    if (j != qp) {
+                        const Point p = qa.pts[j];
+                        const float d2 = sq_dist(q.x, q.y, p.x, p.y);
+                        seed = key_max(seed, ((uint64_t)__float_as_uint(d2) << 32) | p.id);
+                    }
+                }
+            }
+            ln.sel.set_cap(seed + 1);
+        }
+        if (!ln.active) ln.sel.set_cap(0);
+    }
 
     // Own leaves of the wavefront's queries: a contiguous run of leaves.
     const int32_t my_leaf = qa.leaf_of[qp];
@@ -275,7 +363,17 @@ __global__ __launch_bounds__(256) void k_knn_tiles(QueryArgs qa)
         right = !right;
     }
 
-    if (wave_any(ln.sel.cnt > 0)) ln.sel.merge();
+    if (wave_any(ln.sel.cnt > 0)) {
+        ln.sel.merge();
+        ++ln.n_merge;
+    }
+    if (qa.counters && lane == 0) {
+        atomicAdd(&qa.counters[0], (unsigned long long)ln.n_cand);
+        atomicAdd(&qa.counters[1], (unsigned long long)ln.n_merge);
+        atomicAdd(&qa.counters[2], (unsigned long long)ln.n_node);
+        atomicAdd(&qa.counters[3], (unsigned long long)ln.n_leaf);
+        atomicAdd(&qa.counters[4], 1ull);
+    }
 
     if (!ln.active) return;
     const int64_t off = qa.row_off ? qa.row_off[row] : (int64_t)row * qa.k_uniform;
@@ -330,21 +428,24 @@ void launch_knn(const QueryArgs &qa, int kclass, hipStream_t s)
 __global__ void k_query_keys(const int32_t *__restrict__ issuers, const int32_t *__restrict__ ks,
                              uint32_t nq, uint32_t n, int k_max, const int32_t *__restrict__ inv,
                              uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
-                             uint32_t *__restrict__ kcount, IndexCounters *__restrict__ ctr)
+                             uint32_t *__restrict__ kcount, IndexCounters *__restrict__ ctr,
+                             uint64_t *__restrict__ ws, int64_t ws_words, uint32_t epoch)
 {
-    uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    // The query sort and scan workspace starts at zero.
+    for (int64_t w = q; w < ws_words; w += (int64_t)gridDim.x * blockDim.x) ws[w] = 0ull;
     if (q >= nq) return;
     if (issuers) {
         int32_t s = issuers[q];
         bool ok = s >= 0 && (uint32_t)s < n;
-        if (!ok) atomicOr(&ctr->bad_input, 2u);
+        if (!ok) atomicMax(&ctr->bad_issuer, epoch);
         keys[q] = ok ? (uint32_t)inv[s] : 0u;
         vals[q] = q;
     }
     if (ks) {
         int32_t k = ks[q];
         bool ok = k >= 1 && k <= k_max;
-        if (!ok) atomicOr(&ctr->bad_input, 4u);
+        if (!ok) atomicMax(&ctr->bad_k, epoch);
         kcount[q] = ok ? (uint32_t)k : 1u;
     }
 }
@@ -363,13 +464,13 @@ void launch_query_prep(const QueryPrep &p, hipStream_t s)
     const uint32_t g = (p.nq + T - 1) / T;
     if (p.nq == 0) return;
     k_query_keys<<<g, T, 0, s>>>(p.issuers, p.ks, p.nq, p.n, p.k_max, p.inv, p.sort.keys[0],
-                                 p.sort.vals[0], p.kcount, p.ctr);
+                                 p.sort.vals[0], p.kcount, p.ctr, p.ws, p.ws_words, p.epoch);
 }
 
-void launch_offsets(const uint32_t *kcount, uint32_t nq, uint32_t *scan_out, uint32_t *scan_tmp,
+void launch_offsets(const uint32_t *kcount, uint32_t nq, uint32_t *scan_out, const ScanSpace &sp,
                     uint32_t *total, int64_t *offsets, hipStream_t s)
 {
-    launch_exclusive_scan(kcount, scan_out, nq, scan_tmp, total, s);
+    launch_exclusive_scan(kcount, scan_out, nq, sp, total, s);
     const int T = 256;
     k_widen_offsets<<<(nq + 1 + T - 1) / T, T, 0, s>>>(scan_out, total, nq, offsets);
 }

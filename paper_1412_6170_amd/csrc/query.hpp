@@ -25,6 +25,8 @@ struct QueryArgs {
     int32_t *out_ids;
     float *out_d2;
     int32_t *out_cnt;
+    unsigned long long *counters;  // null, or [candidate steps, merges,
+                                   // node visits, leaf sweeps, wavefronts]
 };
 
 struct QueryPrep {
@@ -36,12 +38,15 @@ struct QueryPrep {
     SortBuffers sort;            // keys[0]/vals[0] receive (sorted position, query)
     uint32_t *kcount;            // range-checked k per query
     IndexCounters *ctr;
+    uint64_t *ws;                // query workspace words to zero first
+    int64_t ws_words;
+    uint32_t epoch;              // query epoch for the error flags
 };
 
 int k_class(int k);
 void launch_knn(const QueryArgs &qa, int kclass, hipStream_t s);
 void launch_query_prep(const QueryPrep &p, hipStream_t s);
-void launch_offsets(const uint32_t *kcount, uint32_t nq, uint32_t *scan_out, uint32_t *scan_tmp,
+void launch_offsets(const uint32_t *kcount, uint32_t nq, uint32_t *scan_out, const ScanSpace &sp,
                     uint32_t *total, int64_t *offsets, hipStream_t s);
 
 }  // namespace mknn

@@ -69,3 +69,14 @@ def test_missing_library_raises(monkeypatch):
     monkeypatch.setattr(binding, "LIB_PATH", "/nonexistent/libmknn.so")
     with pytest.raises(ImportError):
         binding.lib()
+
+
+def test_footprint_is_host_only_and_monotone():
+    small = binding.footprint(n_max=10_000, k_max=8)
+    big = binding.footprint(n_max=1_000_000, k_max=32, leaf_capacity=32)
+    more_k = binding.footprint(n_max=1_000_000, k_max=64, leaf_capacity=32)
+    assert 0 < small < big < more_k
+    # results alone take 8 bytes per slot
+    assert big > 1_000_000 * 32 * 8
+    with pytest.raises(binding.MknnError):
+        binding.footprint(n_max=0)
