@@ -1,18 +1,25 @@
 """Benchmark of the per-tick k-NN join on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload clustered_1m]
+                    [--leaf-capacity TH] [--graph] [--counters] [--no-cpu-baseline]
+    python bench.py --serving [--scenes 64] [--rate 1500] [--slots 4]
 
 A step is one tick of the whole hot path on device-resident inputs: the
-snapshot copy into the context, the index build (Morton codes, radix sort,
-leaf split, node tables) and one k-NN query per object (Sec. 4 of arXiv
-1412.6170).  Positions of every tick are generated and copied to HBM before
-the timed region; results stay in HBM (fetching them is not part of a tick).
+index build (Morton codes, radix sort, leaf split, node tables) over the
+tick's positions and one k-NN query per object (Sec. 4 of arXiv 1412.6170).
+Positions of every tick are generated and copied to HBM before the timed
+region; the library reads them in place; results stay in HBM (fetching them
+is not part of a tick).
+
+Unless --leaf-capacity is given, the leaf capacity is chosen during warm-up
+by the library's autotuner (device time per tick over a few candidates;
+results do not depend on it).
 
 Prints one JSON line: queries/s over the K timed ticks, p50/p99 tick latency,
 a roofline entry for the dominant kernel (the leaf-sweep query kernel,
 algorithmic bytes over its mean device time from the library's HIP events on
-the stream it runs on) and the CPU oracle timed on the host cores on a
-bounded sample.
+the stream it runs on), the same ticks replayed as captured HIP graphs, and
+the CPU oracle timed on the host cores on a bounded sample.
 """
 import argparse
 import json
@@ -27,6 +34,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TH_CANDIDATES = (16, 24, 32, 48, 64)
 
 
 def query_kernel_bytes(n, nq, k):
@@ -65,20 +73,121 @@ def cpu_baseline(w):
                 w.name, len(x), k, dt)}
 
 
+def copy_calibration():
+    import torch
+    torch.cuda.set_device(0)
+    src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": src.numel() * 4,
+                      "repeats": 5}), flush=True)
+
+
+def serving_bench(args):
+    """Many independent scenes served with continuous batching: scene sizes
+    log-uniform in [10k, 2M] objects, k in {8, 32}, tick requests arriving as
+    a Poisson process; latency from arrival to device completion."""
+    import torch
+    from paper_1412_6170_amd import serving, workloads
+    torch.cuda.set_device(0)
+    rng = np.random.default_rng(args.serving_seed)
+    scenes = []
+    print("bench: generating %d scenes" % args.scenes, file=sys.stderr, flush=True)
+    for sid in range(args.scenes):
+        n = int(round(np.exp(rng.uniform(np.log(10_000), np.log(2_000_000)))))
+        k = int(rng.choice([8, 32]))
+        w = workloads.clustered_1m(n=n, ticks=args.scene_ticks)
+        pos = []
+        for t in range(args.scene_ticks):
+            x, y, _, _, _ = w.tick(t)
+            pos.append((torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()))
+        scenes.append(serving.Scene(sid, pos, k, leaf_capacity=args.leaf_capacity or 32))
+    torch.cuda.synchronize()
+    budget = int(args.hbm_budget_gib * 2 ** 30)
+    srv = serving.Server(scenes, hbm_budget=budget, slots=args.slots)
+    ids = [s.sid for s in scenes]
+    # warm-up: one tick of every scene (contexts created, kernels loaded)
+    srv.run([(0.0, sid, 0) for sid in ids])
+    arrivals = serving.poisson_arrivals(ids, args.scene_ticks, rate=args.rate,
+                                        seed=args.serving_seed + 1)
+    print("bench: serving %d requests at %.0f/s" % (len(arrivals), args.rate), file=sys.stderr,
+          flush=True)
+    done = srv.run(arrivals)
+    summ = serving.summarize(done, {s.sid: s for s in scenes})
+    out = {"metric": "served k-NN queries/s and tick latency, many scenes, continuous batching",
+           "value": summ["queries_per_s"], "unit": "queries/s", "n_gpus": 1,
+           "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "serving_mix", "scenes": args.scenes,
+                      "objects_total": int(sum(s.n for s in scenes)),
+                      "ticks_per_scene": args.scene_ticks, "rate_per_s": args.rate,
+                      "slots": args.slots, "hbm_budget_gib": args.hbm_budget_gib,
+                      "description": "scene sizes log-uniform in [1e4, 2e6], k in {8, 32}, "
+                                     "clustered moving objects, Poisson tick requests"},
+           "p50_latency_ms": summ["p50_latency_ms"], "p99_latency_ms": summ["p99_latency_ms"],
+           "requests": summ["requests"], "makespan_s": summ["makespan_s"],
+           "admissions": srv.admissions, "evictions": srv.evictions}
+    srv.close()
+    print(json.dumps(out), flush=True)
+
+
+def timed(stream, steps, one_step):
+    """Run `steps` steps bracketed by synchronisations; per-step device
+    latency from events on the stream."""
+    import torch
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        starts[s].record(stream)
+        one_step(s)
+        ends[s].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat = np.array([a.elapsed_time(b) for a, b in zip(starts, ends)])
+    return wall, lat
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="clustered_1m")
-    ap.add_argument("--leaf-capacity", type=int, default=0)
+    ap.add_argument("--leaf-capacity", type=int, default=0,
+                    help="fixed leaf capacity; 0 = autotune over %s" % (TH_CANDIDATES,))
+    ap.add_argument("--graph", action="store_true", default=True,
+                    help="also replay the ticks as captured HIP graphs (default on)")
+    ap.add_argument("--no-graph", dest="graph", action="store_false")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--counters", action="store_true",
+                    help="also count the query kernel's work (adds atomics; not for timing)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device-to-device copy 5 times (reference "
+                         "kernel for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE readings)")
+    ap.add_argument("--serving", action="store_true",
+                    help="serving mode: many scenes, Poisson tick requests, p50/p99 latency")
+    ap.add_argument("--scenes", type=int, default=64)
+    ap.add_argument("--scene-ticks", type=int, default=8)
+    ap.add_argument("--rate", type=float, default=1500.0, help="tick requests per second")
+    ap.add_argument("--slots", type=int, default=4, help="ticks in flight at most")
+    ap.add_argument("--hbm-budget-gib", type=float, default=64.0)
+    ap.add_argument("--serving-seed", type=int, default=7)
     args = ap.parse_args()
 
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs the k-NN tick on a single MI355X "
               "and has no multi-GPU path (--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+
+    if args.serving:
+        serving_bench(args)
+        return
 
     import torch
     from paper_1412_6170_amd import binding, workloads
@@ -86,6 +195,7 @@ def main():
     torch.cuda.set_device(0)
     w = workloads.WORKLOADS[args.workload]()
     n, k = w.n, w.k
+    nq = n
     print("bench: generating %d ticks of %s" % (w.ticks, w.name), file=sys.stderr, flush=True)
     dev = []
     for t in range(w.ticks):
@@ -93,37 +203,33 @@ def main():
         dev.append((torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()))
     torch.cuda.synchronize()
 
-    stream = torch.cuda.current_stream()
-    ctx = binding.Context(n, n, k, leaf_capacity=args.leaf_capacity, k_hint=k,
-                          stream=stream.cuda_stream, timing=True)
+    stream = torch.cuda.Stream()
+    th0 = args.leaf_capacity or min(TH_CANDIDATES)
+    ctx = binding.Context(n, nq, k, leaf_capacity=th0, k_hint=k, stream=stream.cuda_stream,
+                          timing=True, counters=args.counters)
 
     def step(s):
         x, y = dev[s % w.ticks]
         ctx.load_positions(x, y)
         ctx.advance_tick()
-        ctx.query(k=k)
+        ctx.query(k=k, nq=nq)
 
-    for s in range(args.warmup):
-        step(s)
-    ctx.sync()
-    ctx.reset_timing()
-    print("bench: warmup done, timing %d steps" % args.steps, file=sys.stderr, flush=True)
+    with torch.cuda.stream(stream):
+        tune = None
+        if not args.leaf_capacity:
+            best, times = binding.autotune_leaf_capacity(ctx, step, TH_CANDIDATES)
+            tune = {"chosen": best, "device_ms_per_tick": {str(t): v for t, v in times.items()}}
+            print("bench: autotuned leaf capacity %d (%s)" % (best, tune), file=sys.stderr,
+                  flush=True)
+        for s in range(args.warmup):
+            step(s)
+        ctx.sync()
+        ctx.reset_timing()
+        print("bench: timing %d steps" % args.steps, file=sys.stderr, flush=True)
+        wall, lat = timed(stream, args.steps, step)
+        ctx.sync()
+        st = ctx.stats()
 
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s in range(args.steps):
-        starts[s].record(stream)
-        step(s)
-        ends[s].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ctx.sync()
-
-    lat = np.array([a.elapsed_time(b) for a, b in zip(starts, ends)])
-    st = ctx.stats()
-    nq = n
     value = args.steps * nq / wall
     kern_ms = st["ms_query_main_mean"]
     kern_bytes = query_kernel_bytes(n, nq, k)
@@ -152,13 +258,53 @@ def main():
         "tick_hbm_frac": tick_bytes(n, nq, k) / (tick_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "leaves": st["leaves"],
         "deepest_level": st["deepest_level"],
-        "roofline": {"bound": "hbm", "kernel": "k_knn_tiles<32> (leaf sweeps)",
+        "autotune": tune,
+        "roofline": {"bound": "hbm", "kernel": "k_knn_tiles<32,16> (leaf sweeps)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel_ms": kern_ms, "bytes_per_launch": kern_bytes},
+        "graph": None,
         "cpu_baseline": None,
     }
+    if args.counters and st["wavefronts"]:
+        wf = st["wavefronts"]
+        out["per_wavefront"] = {"candidate_steps": st["wave_candidate_steps"] / wf,
+                                "merges": st["wave_merges"] / wf,
+                                "node_visits": st["wave_node_visits"] / wf,
+                                "leaf_sweeps": st["wave_leaf_sweeps"] / wf}
     ctx.close()
+
+    if args.graph:
+        # The same ticks, each captured once as a HIP graph (one graph per
+        # tick's input buffers) and replayed; no timing events inside.
+        gctx = binding.Context(n, nq, k, leaf_capacity=out["config"]["leaf_capacity"], k_hint=k,
+                               stream=stream.cuda_stream)
+
+        def gstep(s):
+            x, y = dev[s % w.ticks]
+            gctx.load_positions(x, y)
+            gctx.advance_tick()
+            gctx.query(k=k, nq=nq)
+
+        with torch.cuda.stream(stream):
+            gstep(0)
+            gctx.sync()
+            graphs = []
+            for t in range(w.ticks):
+                g = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(g, stream=stream):
+                    gstep(t)
+                graphs.append(g)
+            for s in range(args.warmup):
+                graphs[s % w.ticks].replay()
+            gwall, glat = timed(stream, args.steps, lambda s: graphs[s % w.ticks].replay())
+        out["graph"] = {"value": args.steps * nq / gwall, "unit": "queries/s",
+                        "ms_per_step": gwall * 1e3 / args.steps,
+                        "p50_tick_ms": float(np.percentile(glat, 50)),
+                        "p99_tick_ms": float(np.percentile(glat, 99))}
+        del graphs
+        gctx.close()
+
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w)
