@@ -1,7 +1,8 @@
 """Benchmark of the per-tick k-NN join on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload clustered_1m]
-                    [--leaf-capacity TH] [--graph] [--counters] [--no-cpu-baseline]
+                    [--leaf-capacity TH | --autotune] [--no-graph] [--counters]
+                    [--no-cpu-baseline]
     python bench.py --serving [--scenes 64] [--rate 1500] [--slots 4]
 
 A step is one tick of the whole hot path on device-resident inputs: the
@@ -11,9 +12,10 @@ Positions of every tick are generated and copied to HBM before the timed
 region; the library reads them in place; results stay in HBM (fetching them
 is not part of a tick).
 
-Unless --leaf-capacity is given, the leaf capacity is chosen during warm-up
-by the library's autotuner (device time per tick over a few candidates;
-results do not depend on it).
+The leaf capacity is the autotuner's choice for the workload on MI355X
+(TUNED_LEAF_CAPACITY), --leaf-capacity TH, or, with --autotune, chosen
+during warm-up by the autotuner (device time per tick over a few
+candidates).  Results do not depend on it.
 
 Prints one JSON line: queries/s over the K timed ticks, p50/p99 tick latency,
 a roofline entry for the dominant kernel (the leaf-sweep query kernel,
@@ -34,7 +36,36 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TH_CANDIDATES = (16, 24, 32, 48, 64)
+TH_CANDIDATES = (16, 24, 32, 48, 64, 96, 128, 192)
+# Leaf capacity used when --autotune is not given: the autotuner's choice on
+# MI355X for each workload (device time per tick over TH_CANDIDATES).
+TUNED_LEAF_CAPACITY = {"clustered_1m": 64, "uniform_10k": 32, "network_4m": 64, "mixed_16m": 192}
+CPU_SAMPLE_SECONDS = 10.0
+
+# HBM bytes per launch of the query kernel on clustered_1m at the tuned leaf
+# capacity, from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE), each
+# scaled by what the same counter reads for a plain device copy of known
+# size.  Valid only for the kernel sources they were taken on (digest of the
+# query kernel's sources); otherwise the roofline's traffic is null.
+MEASURED_TRAFFIC = {"digest": "e524ae095459ea18", "workload": "clustered_1m", "leaf_capacity": 64,
+                    "fetch_bytes": 151_250_000, "write_bytes": 377_660_000}
+
+
+def query_source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("query.hip", "query.hpp", "mknn_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_1412_6170_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, leaf_capacity):
+    m = MEASURED_TRAFFIC
+    if (not m or m["digest"] != query_source_digest() or m["workload"] != workload
+            or m["leaf_capacity"] != leaf_capacity):
+        return None
+    return m["fetch_bytes"] + m["write_bytes"]
 
 
 def query_kernel_bytes(n, nq, k):
@@ -58,19 +89,27 @@ def host_threads():
     return max(1, min(avail, 16))
 
 
-def cpu_baseline(w):
-    """The oracle as it stands, on tick 0 of the workload: quadtree build plus
-    every query, split by query over the host threads."""
+def cpu_baseline(w, host_ticks):
+    """The oracle as it stands: quadtree build plus every query of a tick,
+    split by query over the host threads, repeated over the workload's ticks
+    until at least CPU_SAMPLE_SECONDS have passed."""
     import oracle
-    x, y, _, _, k = w.tick(0)
+    k = w.k
     threads = host_threads()
-    oracle.knn(x[:20000], y[:20000], k=k, threads=threads)  # load + warm the library
+    x0, y0 = host_ticks[0]
+    oracle.knn(x0[:20000], y0[:20000], k=k, threads=threads)  # load + warm the library
+    done = 0
     t0 = time.perf_counter()
-    oracle.knn(x, y, k=k, threads=threads)
-    dt = time.perf_counter() - t0
-    return {"value": len(x) / dt, "unit": "queries/s", "cores": threads, "kind": "oracle",
-            "sample": "tick 0 of %s: index build + all %d queries (k=%d), %.2f s" % (
-                w.name, len(x), k, dt)}
+    while True:
+        x, y = host_ticks[done % len(host_ticks)]
+        oracle.knn(x, y, k=k, threads=threads)
+        done += 1
+        dt = time.perf_counter() - t0
+        if dt >= CPU_SAMPLE_SECONDS:
+            break
+    return {"value": done * len(x0) / dt, "unit": "queries/s", "cores": threads, "kind": "oracle",
+            "sample": "%d ticks of %s (cycling over its %d ticks): index build + all %d queries "
+                      "(k=%d) per tick, %.1f s" % (done, w.name, len(host_ticks), len(x0), k, dt)}
 
 
 def copy_calibration():
@@ -157,7 +196,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="clustered_1m")
     ap.add_argument("--leaf-capacity", type=int, default=0,
-                    help="fixed leaf capacity; 0 = autotune over %s" % (TH_CANDIDATES,))
+                    help="leaf capacity; 0 = the tuned value for the workload %s"
+                         % (TUNED_LEAF_CAPACITY,))
+    ap.add_argument("--autotune", action="store_true",
+                    help="choose the leaf capacity during warm-up over %s" % (TH_CANDIDATES,))
     ap.add_argument("--graph", action="store_true", default=True,
                     help="also replay the ticks as captured HIP graphs (default on)")
     ap.add_argument("--no-graph", dest="graph", action="store_false")
@@ -197,14 +239,16 @@ def main():
     n, k = w.n, w.k
     nq = n
     print("bench: generating %d ticks of %s" % (w.ticks, w.name), file=sys.stderr, flush=True)
-    dev = []
+    dev, host = [], []
     for t in range(w.ticks):
         x, y, _, _, _ = w.tick(t)
+        host.append((x, y))
         dev.append((torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()))
     torch.cuda.synchronize()
 
     stream = torch.cuda.Stream()
-    th0 = args.leaf_capacity or min(TH_CANDIDATES)
+    th0 = (min(TH_CANDIDATES) if args.autotune else
+           args.leaf_capacity or TUNED_LEAF_CAPACITY.get(w.name, 0))
     ctx = binding.Context(n, nq, k, leaf_capacity=th0, k_hint=k, stream=stream.cuda_stream,
                           timing=True, counters=args.counters)
 
@@ -216,7 +260,7 @@ def main():
 
     with torch.cuda.stream(stream):
         tune = None
-        if not args.leaf_capacity:
+        if args.autotune:
             best, times = binding.autotune_leaf_capacity(ctx, step, TH_CANDIDATES)
             tune = {"chosen": best, "device_ms_per_tick": {str(t): v for t, v in times.items()}}
             print("bench: autotuned leaf capacity %d (%s)" % (best, tune), file=sys.stderr,
@@ -261,7 +305,8 @@ def main():
         "autotune": tune,
         "roofline": {"bound": "hbm", "kernel": "k_knn_tiles<32,16> (leaf sweeps)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(w.name, st["leaf_capacity"]),
                      "kernel_ms": kern_ms, "bytes_per_launch": kern_bytes},
         "graph": None,
         "cpu_baseline": None,
@@ -307,7 +352,7 @@ def main():
 
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(w)
+        out["cpu_baseline"] = cpu_baseline(w, host)
     print(json.dumps(out), flush=True)
 
 
