@@ -15,6 +15,9 @@ Contents (each function names the passage of arXiv 1412.6170 it follows):
   index creation (Sec. 4.1) then a pruned depth-first leaf visit (Sec. 4.2).
 * ``build_index``     -- that index: Morton codes at level 16, objects sorted
   by (code, id), and the non-empty leaves of the PR-quadtree split at ``th``.
+* ``brute_knn_points``, ``knn_points`` -- the same two searches for queries
+  with a free centre q = (x, y, k) in [0,1)^2 (Definition 1) and an optional
+  excluded object id; ``brute_knn_points_numpy`` writes it out in numpy.
 * ``morton_codes``, ``sq_dist`` -- the arithmetic the above rely on.
 
 Result convention (all k-NN entry points): rows in query order, each of
@@ -68,6 +71,11 @@ def lib():
         L.oracle_brute_knn.argtypes = knn_args + [_i32p, _f32p, _i32p, ctypes.c_int32]
         L.oracle_knn.argtypes = knn_args + [ctypes.c_int32, ctypes.c_int32,
                                             _i32p, _f32p, _i32p, ctypes.c_int32]
+        pts_args = [_f32p, _f32p, ctypes.c_int64, _f32p, _f32p, _i32p, _i32p, ctypes.c_int64,
+                    ctypes.c_int32, _i64p]
+        L.oracle_brute_knn_points.argtypes = pts_args + [_i32p, _f32p, _i32p, ctypes.c_int32]
+        L.oracle_knn_points.argtypes = pts_args + [ctypes.c_int32, ctypes.c_int32,
+                                                   _i32p, _f32p, _i32p, ctypes.c_int32]
         _lib = L
     return _lib
 
@@ -214,6 +222,70 @@ def brute_knn_numpy(x, y, issuers=None, k=8):
         dy = y[s] - y
         d2 = dx * dx + dy * dy
         keep = all_ids != s
+        cand_d2 = d2[keep]
+        cand_id = all_ids[keep]
+        order = np.lexsort((cand_id, cand_d2))[:k]
+        m = len(order)
+        ids_out[r, :m] = cand_id[order]
+        d2_out[r, :m] = cand_d2[order]
+        cnt[r] = m
+    return ids_out, d2_out, cnt
+
+
+def _run_points(fn, x, y, qx, qy, exclude, ks, k, extra, threads):
+    x, y = _f32(x), _f32(y)
+    qx, qy = _f32(qx), _f32(qy)
+    n, nq = len(x), len(qx)
+    if len(qy) != nq:
+        raise ValueError("qx and qy differ in length")
+    ex = None if exclude is None else np.ascontiguousarray(exclude, dtype=np.int32)
+    if ex is not None and len(ex) != nq:
+        raise ValueError("exclude must have one entry per query")
+    _, _, kk, ku, offsets, total = _prep_queries(nq, np.zeros(nq, np.int32), ks, k)
+    ids = np.empty(max(total, 1), np.int32)
+    d2 = np.empty(max(total, 1), np.float32)
+    cnt = np.empty(max(nq, 1), np.int32)
+    args = [_ptr(x, _f32p), _ptr(y, _f32p), n, _ptr(qx, _f32p), _ptr(qy, _f32p), _ptr(ex, _i32p),
+            _ptr(kk, _i32p), nq, ku, _ptr(offsets, _i64p)] + extra + [
+                _ptr(ids, _i32p), _ptr(d2, _f32p), _ptr(cnt, _i32p), int(threads)]
+    _check(fn(*args))
+    ids, d2, cnt = ids[:total], d2[:total], cnt[:nq]
+    if ks is None:
+        return ids.reshape(nq, ku), d2.reshape(nq, ku), cnt, None
+    return ids, d2, cnt, offsets
+
+
+def brute_knn_points(x, y, qx, qy, exclude=None, ks=None, k=None, threads=1):
+    """Definition 1 with free centres (qx[i], qy[i]) by brute force (C);
+    object exclude[i] (None or -1: none) is left out.  Rows hold
+    min(k, candidates) entries; same layout as brute_knn."""
+    return _run_points(lib().oracle_brute_knn_points, x, y, qx, qy, exclude, ks, k, [], threads)
+
+
+def knn_points(x, y, qx, qy, exclude=None, ks=None, k=None, th=None, L=16, threads=1):
+    """Sequential PR-quadtree k-NN (Sec. 4) with free centres; same contract
+    as brute_knn_points."""
+    if th is None:
+        kref = int(k) if ks is None else int(np.max(ks)) if len(ks) else 1
+        th = default_leaf_capacity(kref)
+    return _run_points(lib().oracle_knn_points, x, y, qx, qy, exclude, ks, k,
+                       [int(th), int(L)], threads)
+
+
+def brute_knn_points_numpy(x, y, qx, qy, exclude=None, k=8):
+    """Definition 1 with free centres in numpy, uniform k, tiny inputs."""
+    x, y = _f32(x), _f32(y)
+    qx, qy = _f32(qx), _f32(qy)
+    n, nq = len(x), len(qx)
+    ids_out = np.full((nq, k), -1, np.int32)
+    d2_out = np.full((nq, k), np.inf, np.float32)
+    cnt = np.zeros(nq, np.int32)
+    all_ids = np.arange(n, dtype=np.int64)
+    for r in range(nq):
+        dx = qx[r] - x
+        dy = qy[r] - y
+        d2 = dx * dx + dy * dy
+        keep = all_ids != (-1 if exclude is None else int(exclude[r]))
         cand_d2 = d2[keep]
         cand_id = all_ids[keep]
         order = np.lexsort((cand_id, cand_d2))[:k]

@@ -24,6 +24,9 @@
  *     virtual full quadtree at level 16, a sort of the objects by (code, id),
  *     and the level-by-level PR-quadtree split of every quadrant holding more
  *     than th objects, up to the maximum level L (leaves at L may exceed th).
+ *   * oracle_brute_knn_points / oracle_knn_points: the same two searches
+ *     for queries q = (x, y, k) with a free centre in [0,1)^2 (Definition
+ *     1) and an optional excluded object id.
  *   * oracle_knn: a sequential quadtree k-NN over that index: a depth-first
  *     visit that enters children in ascending box lower bound and prunes a
  *     quadrant whose lower bound is strictly greater than the current k-th
@@ -490,6 +493,11 @@ typedef struct {
     const qindex *ix;     /* quadtree search when set */
     const float *x, *y;   /* brute force when ix is NULL */
     int64_t n;
+    /* Free query centres (Definition 1's q = (x, y, k)): when qx is set,
+     * query i is centred on (qx[i], qy[i]) and excludes object exclude[i]
+     * (NULL or -1: nothing excluded); issuers is then unused. */
+    const float *qx, *qy;
+    const int32_t *exclude;
     const int32_t *issuers;
     const int32_t *ks;
     int32_t k_uniform;
@@ -503,12 +511,23 @@ typedef struct {
 
 static void run_one(const batch_job *jb, int64_t q, kheap *h)
 {
-    int32_t s = jb->issuers ? jb->issuers[q] : (int32_t)q;
+    int32_t s;
+    float qx, qy;
+    if (jb->qx) {
+        s = jb->exclude ? jb->exclude[q] : -1;
+        qx = jb->qx[q];
+        qy = jb->qy[q];
+    } else {
+        s = jb->issuers ? jb->issuers[q] : (int32_t)q;
+        qx = jb->x[s];
+        qy = jb->y[s];
+    }
     int32_t k = jb->ks ? jb->ks[q] : jb->k_uniform;
     int64_t off = jb->offsets ? jb->offsets[q] : q * (int64_t)jb->k_uniform;
+    /* Candidates: every object but the excluded one (if any). */
+    int64_t others = jb->n - (s >= 0 ? 1 : 0);
     h->size = 0;
-    h->cap = (int)((int64_t)k < jb->n - 1 ? k : (jb->n > 0 ? jb->n - 1 : 0));
-    float qx = jb->x[s], qy = jb->y[s];
+    h->cap = (int)((int64_t)k < others ? k : (others > 0 ? others : 0));
     if (jb->ix) {
         if (jb->n > 0 && h->cap > 0)
             dfs(jb->ix, 0, qx, qy, s, h);
@@ -554,6 +573,28 @@ static int check_queries(int64_t n, const int32_t *issuers, const int32_t *ks, i
         return OR_EINVAL;
     for (int64_t q = 0; q < nq; ++q) {
         if (issuers && (issuers[q] < 0 || issuers[q] >= n))
+            return OR_EINVAL;
+        if (ks && ks[q] < 1)
+            return OR_EINVAL;
+    }
+    return OR_OK;
+}
+
+/* Free centres: finite, inside [0,1)^2 like the objects; exclude[i] is -1
+ * or an object id. */
+static int check_points(int64_t n, const float *qx, const float *qy, const int32_t *exclude,
+                        const int32_t *ks, int64_t nq, int32_t k_uniform, const int64_t *offsets)
+{
+    if (nq < 0 || !qx || !qy)
+        return OR_EINVAL;
+    if (!ks && k_uniform < 1)
+        return OR_EINVAL;
+    if (ks && !offsets)
+        return OR_EINVAL;
+    for (int64_t q = 0; q < nq; ++q) {
+        if (!(qx[q] >= 0.0f && qx[q] < 1.0f && qy[q] >= 0.0f && qy[q] < 1.0f))
+            return OR_ERANGE;
+        if (exclude && (exclude[q] < -1 || exclude[q] >= n))
             return OR_EINVAL;
         if (ks && ks[q] < 1)
             return OR_EINVAL;
@@ -642,6 +683,71 @@ int oracle_knn(const float *x, const float *y, int64_t n, const int32_t *issuers
     proto.y = y;
     proto.n = n;
     proto.issuers = issuers;
+    proto.ks = ks;
+    proto.k_uniform = k_uniform;
+    proto.offsets = offsets;
+    proto.out_ids = out_ids;
+    proto.out_d2 = out_d2;
+    proto.out_count = out_count;
+    rc = run_batch(&proto, nq, threads);
+    free_index(&ix);
+    return rc;
+}
+
+/* Definition 1 with a free centre: query i is q = (qx[i], qy[i], k_i), and
+ * object exclude[i] (if not NULL and not -1) is left out.  Every other
+ * object is a candidate; ties by id.  Rows hold min(k_i, candidates). */
+int oracle_brute_knn_points(const float *x, const float *y, int64_t n, const float *qx,
+                            const float *qy, const int32_t *exclude, const int32_t *ks,
+                            int64_t nq, int32_t k_uniform, const int64_t *offsets,
+                            int32_t *out_ids, float *out_d2, int32_t *out_count, int32_t threads)
+{
+    int rc = oracle_validate(x, y, n);
+    if (rc)
+        return rc;
+    rc = check_points(n, qx, qy, exclude, ks, nq, k_uniform, offsets);
+    if (rc)
+        return rc;
+    batch_job proto;
+    memset(&proto, 0, sizeof proto);
+    proto.x = x;
+    proto.y = y;
+    proto.n = n;
+    proto.qx = qx;
+    proto.qy = qy;
+    proto.exclude = exclude;
+    proto.ks = ks;
+    proto.k_uniform = k_uniform;
+    proto.offsets = offsets;
+    proto.out_ids = out_ids;
+    proto.out_d2 = out_d2;
+    proto.out_count = out_count;
+    return run_batch(&proto, nq, threads);
+}
+
+/* The quadtree search of oracle_knn with free centres (same contract as
+ * oracle_brute_knn_points). */
+int oracle_knn_points(const float *x, const float *y, int64_t n, const float *qx,
+                      const float *qy, const int32_t *exclude, const int32_t *ks, int64_t nq,
+                      int32_t k_uniform, const int64_t *offsets, int32_t th, int32_t L,
+                      int32_t *out_ids, float *out_d2, int32_t *out_count, int32_t threads)
+{
+    int rc = check_points(n, qx, qy, exclude, ks, nq, k_uniform, offsets);
+    if (rc)
+        return rc;
+    qindex ix;
+    rc = make_index(x, y, n, th, L, &ix);
+    if (rc)
+        return rc;
+    batch_job proto;
+    memset(&proto, 0, sizeof proto);
+    proto.ix = &ix;
+    proto.x = x;
+    proto.y = y;
+    proto.n = n;
+    proto.qx = qx;
+    proto.qy = qy;
+    proto.exclude = exclude;
     proto.ks = ks;
     proto.k_uniform = k_uniform;
     proto.offsets = offsets;
