@@ -20,7 +20,8 @@ candidates).  Results do not depend on it.
 Prints one JSON line: queries/s over the K timed ticks, p50/p99 tick latency,
 a roofline entry for the dominant kernel (the leaf-sweep query kernel,
 algorithmic bytes over its mean device time from the library's HIP events on
-the stream it runs on), the same ticks replayed as captured HIP graphs, and
+the stream it runs on), the same ticks replayed as captured HIP graphs, the
+same ticks with index reuse (refit ticks between rebuilds, Sec. 4.1), and
 the CPU oracle timed on the host cores on a bounded sample.
 """
 import argparse
@@ -204,6 +205,10 @@ def main():
                     help="also replay the ticks as captured HIP graphs (default on)")
     ap.add_argument("--no-graph", dest="graph", action="store_false")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-reuse", dest="reuse", action="store_false", default=True,
+                    help="skip the index-reuse line (refit ticks under the rebuild policy)")
+    ap.add_argument("--reuse-factor", type=float, default=1.3,
+                    help="rebuild when a query takes this factor longer than after the build")
     ap.add_argument("--counters", action="store_true",
                     help="also count the query kernel's work (adds atomics; not for timing)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -349,6 +354,33 @@ def main():
                         "p99_tick_ms": float(np.percentile(glat, 99))}
         del graphs
         gctx.close()
+
+    if args.reuse:
+        # The same ticks with index reuse (Sec. 4.1): refit ticks while the
+        # last query stays within reuse_factor of the time after the last
+        # full build, else rebuild.  The policy reads the previous query's
+        # device time each tick (a host wait inside the timed region).
+        rctx = binding.Context(n, nq, k, leaf_capacity=out["config"]["leaf_capacity"], k_hint=k,
+                               stream=stream.cuda_stream, timing=True)
+        pol = binding.ReusePolicy(factor=args.reuse_factor)
+
+        def rstep(s):
+            x, y = dev[s % w.ticks]
+            pol.tick(rctx, x, y)
+            rctx.query(k=k, nq=nq)
+
+        with torch.cuda.stream(stream):
+            for s in range(args.warmup):
+                rstep(s)
+            pol.rebuilds = pol.refits = 0
+            rwall, rlat = timed(stream, args.steps, rstep)
+        out["reuse"] = {"value": args.steps * nq / rwall, "unit": "queries/s",
+                        "ms_per_step": rwall * 1e3 / args.steps,
+                        "p50_tick_ms": float(np.percentile(rlat, 50)),
+                        "p99_tick_ms": float(np.percentile(rlat, 99)),
+                        "rebuilds": pol.rebuilds, "refits": pol.refits,
+                        "factor": args.reuse_factor}
+        rctx.close()
 
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle", file=sys.stderr, flush=True)

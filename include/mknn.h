@@ -119,6 +119,12 @@ typedef struct mknn_stats {
     int64_t wave_node_visits;     /* node-table entries examined, once per wavefront */
     int64_t wave_leaf_sweeps;     /* leaves swept, once per wavefront */
     int64_t wavefronts;           /* query wavefronts run */
+    /* Index reuse: refit ticks since the last full build, and the largest
+     * per-axis displacement of any object since that build (0 right after
+     * it), by which node boxes are grown during queries. */
+    int64_t refits;
+    float drift;
+    float reserved2;
 } mknn_stats;
 
 /*
@@ -163,6 +169,25 @@ MKNN_API int mknn_load_positions(mknn_ctx *ctx, const float *x, const float *y, 
 MKNN_API int mknn_advance_tick(mknn_ctx *ctx);
 
 /*
+ * mknn_refit_tick -- the index reuse of Sec. 4.1 (the index need not be
+ * rebuilt every tick): instead of a full build, keep the last full build's
+ * object order, leaves and node tables, take every object's position from
+ * the current snapshot and record the largest per-axis displacement D of
+ * any object since that build.  Queries then prune with every node box
+ * grown by D (plus a rounding margin), so results stay exact; they only
+ * get slower as D grows, which is the caller's signal to run a full
+ * mknn_advance_tick again (e.g. when query time grows by a chosen factor
+ * over the time after the last build).  The snapshot must hold as many
+ * objects as at the last full build (ids are positions, so they are the
+ * same objects).  Asynchronous; a bad device coordinate is reported by
+ * the next mknn_sync / mknn_fetch (MKNN_E_RANGE).  mknn_index_fetch after
+ * a refit returns the build's codes and order.
+ * Errors: MKNN_E_STATE (nothing loaded, no full build yet, or a different
+ * object count).
+ */
+MKNN_API int mknn_refit_tick(mknn_ctx *ctx);
+
+/*
  * mknn_query -- enqueue one k-NN query per entry (Sec. 4.2).  Query i is
  * issued by object issuers[i] (NULL = every object 0..n-1, in order, and
  * then nq must equal n), centred on its position and excluding it, and asks
@@ -183,6 +208,26 @@ MKNN_API int mknn_advance_tick(mknn_ctx *ctx);
  */
 MKNN_API int mknn_query(mknn_ctx *ctx, const int32_t *issuers, const int32_t *ks, int64_t nq,
                int32_t k_uniform, int32_t where);
+
+/*
+ * mknn_query_points -- enqueue one k-NN query per entry with a free centre
+ * (Definition 1, Sec. 2.1: a query is q = (x, y, k) for any location).
+ * Query i is centred on (qx[i], qy[i]), which must be finite and inside
+ * [0,1)^2 like the objects; object exclude[i] is left out of its answer
+ * (exclude NULL, or entry -1: nothing is excluded).  ks / k_uniform as for
+ * mknn_query.  qx, qy, exclude and ks are arrays of nq entries in host or
+ * device memory per `where`, read as for mknn_query.  A query of object s
+ * is the query with centre (x[s], y[s]) and exclude s.  Results, their
+ * layout and their lifetime are those of mknn_query (the two share the
+ * result buffers; the last call wins); counts[i] = min(k_i, n - 1) with an
+ * exclusion, min(k_i, n) without.
+ * Errors: MKNN_E_RANGE (bad host centre; a bad device centre is reported
+ * by the next mknn_sync / mknn_fetch), MKNN_E_INVAL (bad exclude or k,
+ * NULL qx or qy, no objects), MKNN_E_STATE, MKNN_E_CAPACITY (as mknn_query).
+ */
+MKNN_API int mknn_query_points(mknn_ctx *ctx, const float *qx, const float *qy,
+                               const int32_t *exclude, const int32_t *ks, int64_t nq,
+                               int32_t k_uniform, int32_t where);
 
 /*
  * mknn_fetch -- synchronise, then copy the last query's results into

@@ -41,7 +41,8 @@ class Stats(ctypes.Structure):
                 ("ms_query_main_mean", ctypes.c_float), ("reserved", ctypes.c_float * 4),
                 ("wave_candidate_steps", ctypes.c_int64), ("wave_merges", ctypes.c_int64),
                 ("wave_node_visits", ctypes.c_int64), ("wave_leaf_sweeps", ctypes.c_int64),
-                ("wavefronts", ctypes.c_int64)]
+                ("wavefronts", ctypes.c_int64), ("refits", ctypes.c_int64),
+                ("drift", ctypes.c_float), ("reserved2", ctypes.c_float)]
 
 
 class MknnError(RuntimeError):
@@ -69,7 +70,9 @@ def lib():
             "mknn_destroy": ([_vp], _i32),
             "mknn_load_positions": ([_vp, _vp, _vp, _i64, _i32], _i32),
             "mknn_advance_tick": ([_vp], _i32),
+            "mknn_refit_tick": ([_vp], _i32),
             "mknn_query": ([_vp, _vp, _vp, _i64, _i32, _i32], _i32),
+            "mknn_query_points": ([_vp, _vp, _vp, _vp, _vp, _i64, _i32, _i32], _i32),
             "mknn_fetch": ([_vp, _vp, _vp, _vp, _vp, _i32], _i32),
             "mknn_result_size": ([_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64)], _i32),
             "mknn_result_device": ([_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
@@ -214,6 +217,11 @@ class Context:
     def advance_tick(self):
         self._check(lib().mknn_advance_tick(self._h))
 
+    def refit_tick(self):
+        """Reuse the last full build's index with the current positions
+        (exact; node boxes grow by the objects' drift since that build)."""
+        self._check(lib().mknn_refit_tick(self._h))
+
     def query(self, k=None, issuers=None, ks=None, nq=None):
         pi, wi, ki = self._arg(issuers, np.int32)
         pk, wk, kk = self._arg(ks, np.int32)
@@ -230,6 +238,27 @@ class Context:
         self._check(lib().mknn_query(self._h, pi, pk, int(nq), int(k or 0), where))
         self._qkeep = [ki, kk]
         self._last_k = None if ks is not None else int(k)
+        self._queried = True
+
+    def query_points(self, qx, qy, exclude=None, k=None, ks=None):
+        """Queries with free centres (qx[i], qy[i]) in [0,1)^2; object
+        exclude[i] (None or -1: none) is left out.  Arrays are numpy (host)
+        or torch CUDA tensors (device), all in the same place."""
+        px, wx, kx = self._arg(qx, np.float32)
+        py, wy, ky = self._arg(qy, np.float32)
+        pe, we, ke = self._arg(exclude, np.int32)
+        pk, wk, kk = self._arg(ks, np.int32)
+        places = {w for w in (wx, wy, we, wk) if w is not None}
+        if len(places) > 1:
+            raise TypeError("query arrays must all live in the same place")
+        where = places.pop() if places else MKNN_HOST
+        nq = len(kx)
+        if len(ky) != nq or (ke is not None and len(ke) != nq) or (kk is not None and len(kk) != nq):
+            raise ValueError("query arrays differ in length")
+        self._check(lib().mknn_query_points(self._h, px, py, pe, pk, int(nq), int(k or 0), where))
+        self._qkeep = [kx, ky, ke, kk]
+        self._last_k = None if ks is not None else int(k)
+        self._queried = True
 
     def result_size(self):
         nq, ne = _i64(), _i64()
@@ -288,6 +317,10 @@ class Context:
     def set_leaf_capacity(self, th):
         self._check(lib().mknn_set_leaf_capacity(self._h, int(th)))
 
+    def stats_ready(self):
+        """True once the context has run a query (stats then describe it)."""
+        return getattr(self, "_queried", False)
+
     def stats(self):
         s = Stats()
         self._check(lib().mknn_get_stats(self._h, ctypes.byref(s)))
@@ -313,6 +346,48 @@ class Context:
         m = nl.value
         return {"codes": codes[:n], "ids": ids[:n], "leaf_level": lev[:m], "leaf_prefix": pre[:m],
                 "leaf_begin": beg[:m], "leaf_end": end[:m], "nodes": st["nodes"]}
+
+
+class ReusePolicy:
+    """When to rebuild the index (Sec. 4.1: rebuild only when the work of the
+    last tick exceeds that of recent ticks by some factor).  After a full
+    build the first query's device time is the reference; later ticks refit
+    the index while the last query stays within ``factor`` times that
+    reference (and at most ``max_refits`` ticks in a row), otherwise they
+    rebuild.  Needs a context created with timing=True; ``tick`` reads the
+    previous query's time (waiting for it to finish) before it loads the new
+    positions, since a load starts a new tick."""
+
+    def __init__(self, factor=1.3, max_refits=None):
+        self.factor = float(factor)
+        self.max_refits = max_refits
+        self.reference = None
+        self.rebuilds = 0
+        self.refits = 0
+        self._after_build = False
+
+    def tick(self, ctx, x, y):
+        """Load the tick's positions and enqueue its index step."""
+        last = None
+        if ctx.stats_ready():
+            st = ctx.stats()
+            last = st["ms_query"] if st["nq"] else None
+            if self._after_build and last:
+                self.reference = last
+        self._after_build = False
+        refits = ctx.stats()["refits"] if last is not None else 0
+        refit = (self.reference is not None and last is not None
+                 and last <= self.factor * self.reference
+                 and (self.max_refits is None or refits < self.max_refits))
+        ctx.load_positions(x, y)
+        if refit:
+            ctx.refit_tick()
+            self.refits += 1
+        else:
+            ctx.advance_tick()
+            self.rebuilds += 1
+            self._after_build = True
+        return "refit" if refit else "build"
 
 
 def autotune_leaf_capacity(ctx, run_tick, candidates, repeats=3):

@@ -30,6 +30,9 @@ struct mknn_ctx {
     bool var_k = false;
     int64_t ticks = 0;
 
+    bool built = false;        // a full build exists (refit ticks may follow)
+    int64_t built_n = 0;       // object count of that build
+    int64_t refits = 0;        // refit ticks since it
     float *x = nullptr, *y = nullptr;           // copies of host-supplied positions
     const float *src_x = nullptr, *src_y = nullptr;  // positions the next build reads
     uint32_t build_epoch = 0, query_epoch = 0;  // tags of the device flags
@@ -38,6 +41,8 @@ struct mknn_ctx {
     Workspace qws{};           // its workspace (and the offsets scan's)
     ScanSpace qscan{};
     int32_t *issuers = nullptr, *ks = nullptr;  // staging of host query arrays
+    float *qcx = nullptr, *qcy = nullptr;       // staging of host free centres
+    QPoint *qpts = nullptr;                     // free centres in processing order
     uint32_t *kcount = nullptr, *kscan = nullptr, *ktotal = nullptr;
     int64_t *offsets = nullptr;
     int32_t *out_ids = nullptr;
@@ -138,10 +143,16 @@ int check_deferred(mknn_ctx *c)
         return fail(c, MKNN_E_RANGE, "a device coordinate is not finite or outside [0,1)%s");
     if (h.bad_nodes == c->build_epoch)
         return fail(c, MKNN_E_DEVICE, "node table capacity exceeded%s");
+    if (h.bad_sync_build == c->build_epoch)
+        return fail(c, MKNN_E_DEVICE, "index build: a look-back wait gave up%s");
+    if (c->queried && h.bad_sync_query == c->query_epoch)
+        return fail(c, MKNN_E_DEVICE, "query indexing: a look-back wait gave up%s");
     if (c->queried && h.bad_issuer == c->query_epoch)
         return fail(c, MKNN_E_INVAL, "a device issuer is outside [0,n)%s");
     if (c->queried && h.bad_k == c->query_epoch)
         return fail(c, MKNN_E_INVAL, "a device k is outside [1,k_max]%s");
+    if (c->queried && h.bad_centre == c->query_epoch)
+        return fail(c, MKNN_E_RANGE, "a device query centre is not finite or outside [0,1)%s");
     return MKNN_OK;
 }
 
@@ -162,6 +173,8 @@ void for_each_buffer(mknn_ctx *c, F &&f)
     f(c->ix.sort.vals[1], N);
     f(c->ix.ws.base, c->ix.ws.cap_words);
     f(c->qws.base, c->qws.cap_words);
+    f(c->ix.xy, N);
+    f(c->ix.anchor, N);
     f(c->ix.pts, N);
     f(c->ix.inv, N);
     f(c->ix.leaf_of, N);
@@ -183,6 +196,9 @@ void for_each_buffer(mknn_ctx *c, F &&f)
     f(c->qs.vals[1], Q);
     f(c->issuers, Q);
     f(c->ks, Q);
+    f(c->qcx, Q);
+    f(c->qcy, Q);
+    f(c->qpts, Q);
     f(c->kcount, Q);
     f(c->kscan, Q);
     f(c->ktotal, 1);
@@ -405,7 +421,197 @@ int mknn_advance_tick(mknn_ctx *c)
     c->ticked = true;
     c->queried = false;
     c->inv_ready = false;
+    c->built = true;
+    c->built_n = c->n;
+    c->refits = 0;
     ++c->ticks;
+    return MKNN_OK;
+}
+
+int mknn_refit_tick(mknn_ctx *c)
+{
+    if (!c) return MKNN_E_INVAL;
+    if (c->dead) return fail(c, MKNN_E_DEVICE, "context has a sticky device error%s");
+    if (!c->loaded) return fail(c, MKNN_E_STATE, "refit_tick before load_positions%s");
+    if (!c->built) return fail(c, MKNN_E_STATE, "refit_tick needs a full build first%s");
+    if (c->n != c->built_n)
+        return fail(c, MKNN_E_STATE, "refit_tick needs the object count of the last build%s");
+    HIP_OR_FAIL(c, hipSetDevice(c->cfg.device));
+    int rc = mark(c, 0);
+    if (rc) return rc;
+    c->build_epoch = next_epoch(c->build_epoch);
+    launch_refit(c->ix, c->src_x, c->src_y, c->n, c->build_epoch, c->stream);
+    rc = check_launch(c, "refit");
+    if (!rc) rc = mark(c, 1);
+    if (rc) return rc;
+    ++c->ring_build;
+    c->ticked = true;
+    c->queried = false;
+    ++c->refits;
+    ++c->ticks;
+    return MKNN_OK;
+}
+
+namespace {
+
+// Query-kernel arguments shared by both kinds of query.
+QueryArgs base_query_args(mknn_ctx *c, int64_t nq, const int32_t *ks, int32_t k_uniform)
+{
+    QueryArgs qa{};
+    qa.pts = c->ix.pts;
+    qa.n = (uint32_t)c->n;
+    qa.fwd = c->ix.fwd;
+    qa.rev = c->ix.rev;
+    qa.leaf_of = c->ix.leaf_of;
+    qa.leaf_begin = c->ix.leaf_begin;
+    qa.leaf_end = c->ix.leaf_end;
+    qa.leaf_node_f = c->ix.leaf_node_f;
+    qa.leaf_node_r = c->ix.leaf_node_r;
+    qa.ctr = c->ix.ctr;
+    qa.node_cap = (int32_t)c->ix.node_cap;
+    qa.nq = (uint32_t)nq;
+    qa.k_uniform = ks ? 0 : k_uniform;
+    qa.out_ids = c->out_ids;
+    qa.out_d2 = c->out_d2;
+    qa.out_cnt = c->out_cnt;
+    qa.counters = (c->cfg.flags & MKNN_FLAG_COUNTERS) ? c->counters : nullptr;
+    qa.build_epoch = c->build_epoch;
+    return qa;
+}
+
+// Host-side description of the results of the query just enqueued.
+void record_query(mknn_ctx *c, int64_t nq, const int32_t *ks, int32_t k_uniform, int32_t where)
+{
+    ++c->ring_query;
+    c->queried = true;
+    c->nq = nq;
+    c->var_k = ks != nullptr;
+    c->k_uniform = ks ? 0 : k_uniform;
+    if (!ks) {
+        c->entries = nq * (int64_t)k_uniform;
+    } else if (where == MKNN_HOST) {
+        int64_t s = 0;
+        for (int64_t i = 0; i < nq; ++i) s += ks[i];
+        c->entries = s;
+    } else {
+        c->entries = -1;  // known after synchronisation
+    }
+}
+
+// Host-side checks of per-query k; *kmax gets the largest.
+int check_host_ks(mknn_ctx *c, const int32_t *ks, int64_t nq, int *kmax)
+{
+    int kmx = 1;
+    for (int64_t i = 0; i < nq; ++i) {
+        if (ks[i] < 1 || ks[i] > c->k_max)
+            return fail(c, MKNN_E_INVAL, "k of query %s outside [1,k_max]",
+                        std::to_string(i).c_str());
+        if (ks[i] > kmx) kmx = ks[i];
+    }
+    *kmax = kmx;
+    return MKNN_OK;
+}
+
+}  // namespace
+
+int mknn_query_points(mknn_ctx *c, const float *qx, const float *qy, const int32_t *exclude,
+                      const int32_t *ks, int64_t nq, int32_t k_uniform, int32_t where)
+{
+    if (!c) return MKNN_E_INVAL;
+    if (c->dead) return fail(c, MKNN_E_DEVICE, "context has a sticky device error%s");
+    if (!valid_where(where)) return fail(c, MKNN_E_INVAL, "bad `where`%s");
+    if (!c->ticked) return fail(c, MKNN_E_STATE, "query before advance_tick%s");
+    if (nq < 0) return fail(c, MKNN_E_INVAL, "nq < 0%s");
+    if (nq > c->cfg.q_max) return fail(c, MKNN_E_CAPACITY, "nq exceeds q_max%s");
+    if (nq > 0 && (!qx || !qy)) return fail(c, MKNN_E_INVAL, "qx and qy are required%s");
+    if (c->n == 0 && nq > 0) return fail(c, MKNN_E_INVAL, "queries need at least one object%s");
+    if (!ks && (k_uniform < 1 || k_uniform > c->k_max))
+        return fail(c, MKNN_E_INVAL, "k outside [1, k_max]%s");
+    int kmax_call = ks ? c->k_max : k_uniform;
+    if (where == MKNN_HOST) {
+        for (int64_t i = 0; i < nq; ++i) {
+            if (!(qx[i] >= 0.0f && qx[i] < 1.0f && qy[i] >= 0.0f && qy[i] < 1.0f))
+                return fail(c, MKNN_E_RANGE, "query centre %s is not finite or outside [0,1)",
+                            std::to_string(i).c_str());
+            if (exclude && (exclude[i] < -1 || exclude[i] >= c->n))
+                return fail(c, MKNN_E_INVAL, "exclude of query %s is not -1 or an object id",
+                            std::to_string(i).c_str());
+        }
+        if (ks) {
+            int rc = check_host_ks(c, ks, nq, &kmax_call);
+            if (rc) return rc;
+        }
+    }
+    HIP_OR_FAIL(c, hipSetDevice(c->cfg.device));
+    int rc = mark(c, 2);
+    if (rc) return rc;
+    c->query_epoch = next_epoch(c->query_epoch);
+
+    const float *d_qx = qx, *d_qy = qy;
+    const int32_t *d_ex = exclude, *d_ks = ks;
+    if (where == MKNN_HOST && nq > 0) {
+        HIP_OR_FAIL(c, hipMemcpyAsync(c->qcx, qx, (size_t)nq * 4, hipMemcpyHostToDevice,
+                                      c->stream));
+        HIP_OR_FAIL(c, hipMemcpyAsync(c->qcy, qy, (size_t)nq * 4, hipMemcpyHostToDevice,
+                                      c->stream));
+        d_qx = c->qcx;
+        d_qy = c->qcy;
+        if (exclude) {
+            HIP_OR_FAIL(c, hipMemcpyAsync(c->issuers, exclude, (size_t)nq * 4,
+                                          hipMemcpyHostToDevice, c->stream));
+            d_ex = c->issuers;
+        }
+        if (ks) {
+            HIP_OR_FAIL(c, hipMemcpyAsync(c->ks, ks, (size_t)nq * 4, hipMemcpyHostToDevice,
+                                          c->stream));
+            d_ks = c->ks;
+        }
+    }
+
+    QueryArgs qa = base_query_args(c, nq, ks, k_uniform);
+    if (nq > 0) {
+        const int64_t words = carve_workspace(c->qws, nq + 1, &c->qs, &c->qscan, 1,
+                                              &c->ix.ctr->bad_sync_query, c->query_epoch);
+        PointPrep p{};
+        p.qx = d_qx;
+        p.qy = d_qy;
+        p.exclude = d_ex;
+        p.ks = d_ks;
+        p.nq = (uint32_t)nq;
+        p.n = (uint32_t)c->n;
+        p.k_max = c->k_max;
+        p.sort = c->qs;
+        p.kcount = c->kcount;
+        p.ctr = c->ix.ctr;
+        p.ws = c->qws.base;
+        p.ws_words = words;
+        p.epoch = c->query_epoch;
+        launch_point_prep(p, c->stream);
+        const int res = launch_radix_sort(c->qs, nq, 2 * kCodeLevels, c->stream);
+        launch_point_place(c->qs.keys[res], c->qs.vals[res], (uint32_t)nq, d_qx, d_qy, d_ex,
+                           c->ix.pts, (uint32_t)c->n, c->qpts, c->stream);
+        qa.qpts = c->qpts;
+        qa.qrow = (const int32_t *)c->qs.vals[res];
+        if (d_ks) {
+            launch_offsets(c->kcount, (uint32_t)nq, c->kscan, c->qscan, c->ktotal, c->offsets,
+                           c->stream);
+            qa.ks = (const int32_t *)c->kcount;
+            qa.row_off = c->offsets;
+        }
+    } else if (d_ks) {
+        const int64_t words = carve_workspace(c->qws, 1, &c->qs, &c->qscan, 1,
+                                              &c->ix.ctr->bad_sync_query, c->query_epoch);
+        launch_zero_words(c->qws.base, words, c->stream);
+        launch_offsets(c->kcount, 0, c->kscan, c->qscan, c->ktotal, c->offsets, c->stream);
+    }
+    rc = mark(c, 4);
+    if (rc) return rc;
+    launch_knn(qa, k_class(kmax_call), c->stream);
+    rc = check_launch(c, "k-NN query");
+    if (!rc) rc = mark(c, 5);
+    if (!rc) rc = mark(c, 3);
+    if (rc) return rc;
+    record_query(c, nq, ks, k_uniform, where);
     return MKNN_OK;
 }
 
@@ -458,31 +664,15 @@ int mknn_query(mknn_ctx *c, const int32_t *issuers, const int32_t *ks, int64_t n
         }
     }
 
-    QueryArgs qa{};
-    qa.pts = c->ix.pts;
-    qa.n = (uint32_t)c->n;
-    qa.fwd = c->ix.fwd;
-    qa.rev = c->ix.rev;
-    qa.leaf_of = c->ix.leaf_of;
-    qa.leaf_begin = c->ix.leaf_begin;
-    qa.leaf_end = c->ix.leaf_end;
-    qa.leaf_node_f = c->ix.leaf_node_f;
-    qa.leaf_node_r = c->ix.leaf_node_r;
-    qa.ctr = c->ix.ctr;
-    qa.node_cap = (int32_t)c->ix.node_cap;
-    qa.nq = (uint32_t)nq;
-    qa.k_uniform = ks ? 0 : k_uniform;
-    qa.out_ids = c->out_ids;
-    qa.out_d2 = c->out_d2;
-    qa.out_cnt = c->out_cnt;
-    qa.counters = (c->cfg.flags & MKNN_FLAG_COUNTERS) ? c->counters : nullptr;
+    QueryArgs qa = base_query_args(c, nq, ks, k_uniform);
 
     if (d_iss && nq > 0 && !c->inv_ready) {
         launch_inverse(c->ix, c->n, c->stream);
         c->inv_ready = true;
     }
     if ((d_iss || d_ks) && nq > 0) {
-        const int64_t words = carve_workspace(c->qws, nq + 1, &c->qs, &c->qscan, 1);
+        const int64_t words = carve_workspace(c->qws, nq + 1, &c->qs, &c->qscan, 1,
+                                              &c->ix.ctr->bad_sync_query, c->query_epoch);
         QueryPrep p{};
         p.issuers = d_iss;
         p.ks = d_ks;
@@ -510,7 +700,8 @@ int mknn_query(mknn_ctx *c, const int32_t *issuers, const int32_t *ks, int64_t n
         }
     } else if (d_ks) {
         // nq == 0 with variable k: a single zero offset.
-        const int64_t words = carve_workspace(c->qws, 1, &c->qs, &c->qscan, 1);
+        const int64_t words = carve_workspace(c->qws, 1, &c->qs, &c->qscan, 1,
+                                              &c->ix.ctr->bad_sync_query, c->query_epoch);
         launch_zero_words(c->qws.base, words, c->stream);
         launch_offsets(c->kcount, 0, c->kscan, c->qscan, c->ktotal, c->offsets, c->stream);
     }
@@ -521,20 +712,7 @@ int mknn_query(mknn_ctx *c, const int32_t *issuers, const int32_t *ks, int64_t n
     if (!rc) rc = mark(c, 5);
     if (!rc) rc = mark(c, 3);
     if (rc) return rc;
-    ++c->ring_query;
-    c->queried = true;
-    c->nq = nq;
-    c->var_k = ks != nullptr;
-    c->k_uniform = ks ? 0 : k_uniform;
-    if (!ks) {
-        c->entries = nq * (int64_t)k_uniform;
-    } else if (where == MKNN_HOST) {
-        int64_t s = 0;
-        for (int64_t i = 0; i < nq; ++i) s += ks[i];
-        c->entries = s;
-    } else {
-        c->entries = -1;  // known after synchronisation
-    }
+    record_query(c, nq, ks, k_uniform, where);
     return MKNN_OK;
 }
 
@@ -701,6 +879,11 @@ int mknn_get_stats(const mknn_ctx *cc, mknn_stats *out)
         out->leaves = c->n > 0 ? h.n_leaves : 0;
         out->nodes = c->n > 0 ? h.n_nodes : 0;
         out->deepest_level = (h.deepest >> 8) == c->build_epoch ? (int32_t)(h.deepest & 0xff) : 0;
+        out->refits = c->refits;
+        if ((uint32_t)(h.drift >> 32) == c->build_epoch) {
+            const uint32_t bits = (uint32_t)h.drift;
+            memcpy(&out->drift, &bits, sizeof bits);
+        }
         if ((c->cfg.flags & MKNN_FLAG_TIMING) && c->have_events) {
             float ms = 0;
             if (hipEventElapsedTime(&ms, c->ev[0], c->ev[1]) == hipSuccess) out->ms_build = ms;

@@ -4,8 +4,9 @@
 //                    quadtree at l_max = 16), x cell in the even bits;
 //                    device-side range validation
 //   radix sort       stable LSD sort of (code, id), 8-bit digits, tiles
-//                    staged in LDS and written back in digit runs
-//   k_gather         sorted objects as 16-byte records {x, y, id, code}
+//                    staged in LDS and written back in digit runs; the
+//                    last pass writes the sorted objects as 16-byte records
+//                    {x, y, id, code}
 //   k_leaf_flags     which adjacent sorted objects fall in different leaves
 //   k_leaf_emit      leaf ranges from the flags' exclusive scan
 //   k_leaf_info      leaf level and the node count each leaf contributes
@@ -137,28 +138,51 @@ __device__ __forceinline__ void lb_publish(uint64_t *status, uint32_t stride, ui
     lb_store(status + (uint64_t)tile * stride, (tile == 0 ? kLbInc : kLbAgg) | agg);
 }
 
-// Exclusive prefix of the tile, then publish the inclusive prefix.
+// Exclusive prefix of the tile, then publish the inclusive prefix.  The
+// predecessors' words are read kLbWindow at a time (independent loads in
+// flight together), then consumed in order: aggregates are added until an
+// inclusive prefix is met; a word not yet published stops the pass and the
+// next read starts from it.
+constexpr int kLbWindow = 8;
+
 __device__ __forceinline__ uint64_t lb_resolve(uint64_t *status, uint32_t stride, uint32_t tile,
-                                               uint64_t agg, uint32_t *err)
+                                               uint64_t agg, uint32_t *err, uint32_t epoch)
 {
     if (tile == 0) return 0;
     uint64_t excl = 0;
-    int64_t t = (int64_t)tile - 1;
+    int64_t t = (int64_t)tile - 1;  // next predecessor to add
     uint32_t spins = 0;
-    while (t >= 0) {
-        const uint64_t w = lb_load(status + (uint64_t)t * stride);
-        const uint64_t flag = w & ~kLbVal;
-        if (flag == 0) {
+    bool done = false;
+    while (!done) {
+        uint64_t w[kLbWindow];
+#pragma unroll
+        for (int i = 0; i < kLbWindow; ++i)
+            w[i] = (t - i >= 0) ? lb_load(status + (uint64_t)(t - i) * stride) : kLbInc;
+        int used = 0;
+        bool stalled = false;
+#pragma unroll
+        for (int i = 0; i < kLbWindow; ++i) {
+            if (!done && !stalled) {
+                const uint64_t flag = w[i] & ~kLbVal;
+                if (flag == 0) {
+                    stalled = true;
+                } else {
+                    excl += w[i] & kLbVal;
+                    ++used;
+                    // Tile 0 is always inclusive, so t - i < 0 is never
+                    // reached; the kLbInc filler above only ends the walk.
+                    if (flag == kLbInc) done = true;
+                }
+            }
+        }
+        t -= used;
+        if (!done && used == 0) {
             if (++spins > kSpinLimit) {
-                atomicOr(err, 1u);
+                atomicMax(err, epoch);
                 break;
             }
             __builtin_amdgcn_s_sleep(1);
-            continue;
         }
-        excl += w & kLbVal;
-        if (flag == kLbInc) break;
-        --t;
     }
     lb_store(status + (uint64_t)tile * stride, kLbInc | (excl + agg));
     return excl;
@@ -200,7 +224,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_lb(const uint32_t *in, ui
     uint32_t pre = block_excl_scan<kScanThreads>(sum, &agg);
     if (threadIdx.x == 0) {
         lb_publish(sp.status, 1, tile, agg);
-        const uint64_t e = lb_resolve(sp.status, 1, tile, agg, sp.err);
+        const uint64_t e = lb_resolve(sp.status, 1, tile, agg, sp.err, sp.epoch);
         s_excl = (uint32_t)e;
         if (total && base + kScanTile >= n) *total = (uint32_t)e + agg;
     }
@@ -245,8 +269,8 @@ void launch_zero_words(uint64_t *p, int64_t words, hipStream_t s)
 
 __global__ void k_morton(const float *__restrict__ x, const float *__restrict__ y, uint32_t n,
                          uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
-                         IndexCounters *__restrict__ ctr, uint64_t *__restrict__ ws,
-                         int64_t ws_words, uint32_t epoch)
+                         float2 *__restrict__ xy, IndexCounters *__restrict__ ctr,
+                         uint64_t *__restrict__ ws, int64_t ws_words, uint32_t epoch)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     // The build's scan and sort workspace starts at zero.
@@ -264,6 +288,9 @@ __global__ void k_morton(const float *__restrict__ x, const float *__restrict__ 
     cy = min(cy, 65535u);
     keys[i] = spread_bits16(cx) | (spread_bits16(cy) << 1);
     vals[i] = i;
+    // Interleaved copy, so the sort's last pass fetches a position with one
+    // 8-byte read.
+    xy[i] = make_float2(px, py);
 }
 
 // ---------------------------------------------------------------------------
@@ -271,15 +298,33 @@ __global__ void k_morton(const float *__restrict__ x, const float *__restrict__ 
 //
 // k_radix_ghist counts every pass's digits over all keys in one read (keys
 // do not change between passes, only their order).  Each pass then runs one
-// kernel: a tile ranks its keys stably in LDS (rounds of 256 keys in
-// position order; within a wavefront, lanes holding the same digit are
-// found with ballots), publishes its per-digit counts, reorders the tile by
-// digit in LDS, finds each digit's offset among earlier tiles by
-// decoupled look-back (one thread per digit) and writes the tile out in
-// contiguous digit runs.
+// kernel over tiles of kSortTile keys:
+//   * wavefront w of the tile owns a contiguous quarter of it and ranks its
+//     keys in rounds of 64 in position order; lanes holding the same digit
+//     are found with ballots, and a wavefront-private LDS counter per digit
+//     gives the rank (no workgroup barrier between rounds);
+//   * per-digit counts of the tile are published for decoupled look-back
+//     and the tile is reordered by digit in LDS;
+//   * each digit's offset among earlier tiles is found by look-back (one
+//     thread per digit) and the tile is written out in contiguous digit
+//     runs.  The last pass of the index build writes the sorted 16-byte
+//     object records directly (positions fetched by id), so no separate
+//     gather follows.
 // ---------------------------------------------------------------------------
 
 constexpr int kGhistItems = 32;  // keys per thread in the histogram kernel
+
+// Lanes of the wavefront (among `valid`) holding the same 8-bit digit d.
+__device__ __forceinline__ uint64_t digit_peers(uint32_t d, uint64_t valid)
+{
+    uint64_t peers = valid;
+#pragma unroll
+    for (int b = 0; b < kRadixBits; ++b) {
+        const uint64_t m = __ballot((d >> b) & 1u);
+        peers &= ((d >> b) & 1u) ? m : ~m;
+    }
+    return peers;
+}
 
 __global__ __launch_bounds__(kSortThreads) void k_radix_ghist(const uint32_t *__restrict__ keys,
                                                              uint32_t n, int passes,
@@ -289,13 +334,22 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_ghist(const uint32_t *__
 #pragma unroll
     for (int p = 0; p < kMaxRadixPasses; ++p) s_h[p][threadIdx.x] = 0;
     __syncthreads();
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint64_t lt_mask = (1ull << lane) - 1ull;
     const uint32_t base = blockIdx.x * (uint32_t)(kSortThreads * kGhistItems);
     for (int j = 0; j < kGhistItems; ++j) {
         const uint32_t i = base + j * kSortThreads + threadIdx.x;
-        if (i < n) {
-            const uint32_t k = keys[i];
-            for (int p = 0; p < passes; ++p)
-                atomicAdd(&s_h[p][(k >> (kRadixBits * p)) & (kRadixBins - 1)], 1u);
+        const bool ok = i < n;
+        const uint64_t valid = __ballot(ok);
+        if (valid == 0ull) break;  // wave-uniform
+        const uint32_t k = ok ? keys[i] : 0u;
+        for (int p = 0; p < passes; ++p) {
+            // One LDS atomic per distinct digit of the wavefront: clustered
+            // codes share their high digits, and same-address atomics
+            // would serialise.
+            const uint32_t d = (k >> (kRadixBits * p)) & (kRadixBins - 1);
+            const uint64_t peers = digit_peers(d, valid);
+            if (ok && (peers & lt_mask) == 0ull) atomicAdd(&s_h[p][d], (uint32_t)__popcll(peers));
         }
     }
     __syncthreads();
@@ -309,76 +363,69 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_pass(
     const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ vals_in,
     uint32_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out, uint32_t n, int shift,
     const uint32_t *__restrict__ ghist, uint64_t *__restrict__ status, uint32_t *__restrict__ ticket,
-    uint32_t *__restrict__ err)
+    uint32_t *__restrict__ err, uint32_t epoch, const float2 *__restrict__ xy,
+    Point *__restrict__ pts, float2 *__restrict__ anchor)
 {
     constexpr int NW = kSortThreads / kWave;
+    constexpr int PER_WAVE = kWave * kSortItems;
     __shared__ uint32_t s_keys[kSortTile];
     __shared__ uint32_t s_vals[kSortTile];
-    __shared__ uint32_t s_start[kRadixBins];
-    __shared__ uint32_t s_run[kRadixBins];
-    __shared__ uint32_t s_base[kRadixBins];
-    __shared__ uint32_t s_wcnt[NW][kRadixBins];
-    __shared__ uint32_t s_wbase[NW][kRadixBins];
+    __shared__ uint32_t s_wc[NW][kRadixBins];  // per-wavefront digit counts, then bases
+    __shared__ uint32_t s_start[kRadixBins];   // start of each digit's run in the tile
+    __shared__ uint32_t s_base[kRadixBins];    // destination of each digit's run
 
     const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
-    const uint32_t tile = take_ticket(ticket);
+#pragma unroll
+    for (int q = 0; q < NW; ++q) s_wc[q][t] = 0;
+    const uint32_t tile = take_ticket(ticket);  // also orders the clearing above
     const uint32_t base = tile * (uint32_t)kSortTile;
     const uint32_t n_valid = min((uint32_t)kSortTile, n - base);
-    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+    const uint64_t lt_mask = (1ull << lane) - 1ull;
 
-    uint32_t key[kSortItems], val[kSortItems];
-    int dig[kSortItems];
+    // Wavefront w owns tile positions [w * PER_WAVE, (w + 1) * PER_WAVE);
+    // round j of lane l holds position w * PER_WAVE + j * 64 + l.  Padding
+    // keys (all ones) take the last digit and the last positions, so they
+    // rank after every real key.
+    uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
 #pragma unroll
     for (int j = 0; j < kSortItems; ++j) {
-        const uint32_t p = j * kSortThreads + t;
+        const uint32_t p = w * PER_WAVE + j * kWave + lane;
         const bool v = p < n_valid;
         key[j] = v ? keys_in[base + p] : 0xffffffffu;
         val[j] = v ? vals_in[base + p] : 0u;
-        // Padding takes the last digit; it sits at the end of the tile's
-        // position order, so it ranks after every real key.
-        dig[j] = v ? (int)((key[j] >> shift) & (kRadixBins - 1)) : kRadixBins - 1;
     }
-
-    s_start[t] = 0;
-    s_run[t] = 0;
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < kSortItems; ++j) atomicAdd(&s_start[dig[j]], 1u);
-    __syncthreads();
-    const uint32_t cnt = s_start[t];
-    // Publish this tile's count of digit t (padding excluded) right away, so
-    // later tiles can resolve while this one ranks.
-    const uint32_t real = cnt - (t == kRadixBins - 1 ? (uint32_t)kSortTile - n_valid : 0u);
-    lb_publish(status + t, kRadixBins, tile, real);
-    __syncthreads();
-    s_start[t] = block_excl_scan<kSortThreads>(cnt, nullptr);
-
 #pragma unroll
     for (int j = 0; j < kSortItems; ++j) {
-        const int d = dig[j];
-        uint64_t peers = ~0ull;
+        const uint32_t d = (key[j] >> shift) & (kRadixBins - 1);
+        const uint64_t peers = digit_peers(d, ~0ull);
+        const uint32_t below = (uint32_t)__popcll(peers & lt_mask);
+        const uint32_t prior = s_wc[w][d];
+        rank[j] = prior + below;
+        // The lowest lane of each digit group advances the counter; the
+        // wavefront's LDS accesses complete in order, so the next round
+        // reads the new value.
+        if (below == 0) s_wc[w][d] = prior + (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+
+    // Thread t: digit t.  Per-wavefront counts become per-wavefront bases.
+    uint32_t cnt = 0;
 #pragma unroll
-        for (int b = 0; b < kRadixBits; ++b) {
-            const uint64_t m = __ballot((d >> b) & 1);
-            peers &= ((d >> b) & 1) ? m : ~m;
-        }
-        const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
+    for (int q = 0; q < NW; ++q) {
+        const uint32_t c = s_wc[q][t];
+        s_wc[q][t] = cnt;
+        cnt += c;
+    }
+    // Publish this tile's count of digit t (padding excluded) before
+    // anything else, so later tiles can resolve while this one reorders.
+    const uint32_t real = cnt - (t == kRadixBins - 1 ? (uint32_t)kSortTile - n_valid : 0u);
+    lb_publish(status + t, kRadixBins, tile, real);
+    s_start[t] = block_excl_scan<kSortThreads>(cnt, nullptr);
+    __syncthreads();
 #pragma unroll
-        for (int q = 0; q < NW; ++q) s_wcnt[q][t] = 0;
-        __syncthreads();
-        if (rank == 0) s_wcnt[w][d] = (uint32_t)__popcll(peers);
-        __syncthreads();
-        {
-            uint32_t r = s_run[t];
-#pragma unroll
-            for (int q = 0; q < NW; ++q) {
-                s_wbase[q][t] = r;
-                r += s_wcnt[q][t];
-            }
-            s_run[t] = r;
-        }
-        __syncthreads();
-        const uint32_t local = s_start[d] + s_wbase[w][d] + rank;
+    for (int j = 0; j < kSortItems; ++j) {
+        const uint32_t d = (key[j] >> shift) & (kRadixBins - 1);
+        const uint32_t local = s_start[d] + s_wc[w][d] + rank[j];
         s_keys[local] = key[j];
         s_vals[local] = val[j];
     }
@@ -386,10 +433,8 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_pass(
     // Offset of digit t: keys of smaller digits anywhere, plus keys of digit
     // t in earlier tiles.
     {
-        uint32_t below;
-        const uint32_t g = ghist[t];
-        below = block_excl_scan<kSortThreads>(g, nullptr);
-        const uint64_t before = lb_resolve(status + t, kRadixBins, tile, real, err);
+        const uint32_t below = block_excl_scan<kSortThreads>(ghist[t], nullptr);
+        const uint64_t before = lb_resolve(status + t, kRadixBins, tile, real, err, epoch);
         s_base[t] = below + (uint32_t)before;
     }
     __syncthreads();
@@ -400,18 +445,37 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_pass(
             const uint32_t k = s_keys[lp];
             const uint32_t d = (k >> shift) & (kRadixBins - 1);
             const uint32_t dst = s_base[d] + (lp - s_start[d]);
+            const uint32_t v = s_vals[lp];
+            // dst < n whenever the digit counts are consistent; a failed
+            // look-back wait (err set) must not turn into a stray write.
+            if (dst >= n) {
+                atomicMax(err, epoch);
+                continue;
+            }
             keys_out[dst] = k;
-            vals_out[dst] = s_vals[lp];
+            if (pts) {
+                const float2 q = xy[v];
+                Point r;
+                r.x = q.x;
+                r.y = q.y;
+                r.id = v;
+                r.code = k;
+                pts[dst] = r;
+                anchor[dst] = q;
+            } else {
+                vals_out[dst] = v;
+            }
         }
     }
 }
 
 int64_t radix_tiles(int64_t n) { return n > 0 ? (n + kSortTile - 1) / kSortTile : 1; }
 
-int launch_radix_sort(const SortBuffers &b, int64_t n, int bits, hipStream_t s)
+int launch_radix_sort(const SortBuffers &b, int64_t n, int bits, hipStream_t s, const float2 *xy,
+                      Point *pts, float2 *anchor)
 {
     int cur = 0;
-    if (n <= 1) return cur;
+    if (n < 1 || (n == 1 && !pts)) return cur;
     const uint32_t ntiles = (uint32_t)radix_tiles(n);
     const int passes = (bits + kRadixBits - 1) / kRadixBits;
     const uint32_t gblocks = (uint32_t)((n + kSortThreads * kGhistItems - 1) / (kSortThreads * kGhistItems));
@@ -420,7 +484,9 @@ int launch_radix_sort(const SortBuffers &b, int64_t n, int bits, hipStream_t s)
         k_radix_pass<<<ntiles, kSortThreads, 0, s>>>(
             b.keys[cur], b.vals[cur], b.keys[cur ^ 1], b.vals[cur ^ 1], (uint32_t)n,
             kRadixBits * p, b.ghist + p * kRadixBins,
-            b.status + (uint64_t)p * ntiles * kRadixBins, b.tickets + p, b.err);
+            b.status + (uint64_t)p * ntiles * kRadixBins, b.tickets + p, b.err, b.epoch,
+            p == passes - 1 ? xy : nullptr, p == passes - 1 ? pts : nullptr,
+            p == passes - 1 ? anchor : nullptr);
         cur ^= 1;
     }
     return cur;
@@ -434,21 +500,23 @@ int64_t workspace_words(int64_t n)
 }
 
 int64_t carve_workspace(const Workspace &ws, int64_t n, SortBuffers *sort, ScanSpace *scans,
-                        int n_scans)
+                        int n_scans, uint32_t *err, uint32_t epoch)
 {
     uint64_t *p = ws.base;
     uint32_t *small = (uint32_t *)p;
     sort->ghist = small;                                   // [4][256]
     sort->tickets = small + kMaxRadixPasses * kRadixBins;  // [4]
-    sort->err = sort->tickets + kMaxRadixPasses;           // [1]
-    uint32_t *scan_tickets = sort->err + 1;                // [n_scans]
+    sort->err = err;
+    sort->epoch = epoch;
+    uint32_t *scan_tickets = sort->tickets + kMaxRadixPasses + 1;  // [n_scans]
     p += (kMaxRadixPasses * kRadixBins + 16 + 8) / 2 + 8;
     sort->status = p;
     p += (int64_t)kMaxRadixPasses * radix_tiles(n) * kRadixBins;
     for (int i = 0; i < n_scans; ++i) {
         scans[i].status = p;
         scans[i].ticket = scan_tickets + i;
-        scans[i].err = sort->err;
+        scans[i].err = err;
+        scans[i].epoch = epoch;
         p += scan_tiles(n);
     }
     return (int64_t)(p - ws.base);
@@ -457,21 +525,6 @@ int64_t carve_workspace(const Workspace &ws, int64_t n, SortBuffers *sort, ScanS
 // ---------------------------------------------------------------------------
 // Sorted objects, leaves and node tables
 // ---------------------------------------------------------------------------
-
-__global__ void k_gather(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ vals,
-                         const float *__restrict__ x, const float *__restrict__ y, uint32_t n,
-                         Point *__restrict__ pts)
-{
-    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    uint32_t id = vals[i];
-    Point p;
-    p.x = x[id];
-    p.y = y[id];
-    p.id = id;
-    p.code = keys[i];
-    pts[i] = p;
-}
 
 // Sorted position of every object id; only subset queries need it.
 __global__ void k_inverse(const Point *__restrict__ pts, uint32_t n, int32_t *__restrict__ inv)
@@ -636,70 +689,74 @@ __device__ __forceinline__ uint32_t gallop_down(const uint32_t *__restrict__ lc,
     return lo;
 }
 
-// The nodes leaf j contributes to both tables.
-__device__ void emit_leaf_nodes(const uint32_t *__restrict__ codes, uint32_t n,
-                                const int32_t *__restrict__ leaf_begin,
-                                const int32_t *__restrict__ leaf_end,
-                                const int32_t *__restrict__ leaf_level,
-                                const uint32_t *__restrict__ leaf_code,
-                                const uint32_t *__restrict__ off_f,
-                                const uint32_t *__restrict__ off_r, uint32_t nl, uint32_t total,
-                                Node *__restrict__ fwd, Node *__restrict__ rev,
-                                int32_t *__restrict__ leaf_node_f,
-                                int32_t *__restrict__ leaf_node_r, uint32_t node_cap, uint32_t j)
+// The level-l node leaf j contributes to either table (if any): leaf j
+// emits its forward nodes (its ancestors below the deepest quadrant shared
+// with leaf j-1, then itself) and its backward nodes (likewise with leaf
+// j+1).  One lane per (leaf, level), so the searches of different levels
+// of one leaf run side by side instead of one after another.
+__device__ __forceinline__ void emit_leaf_level(
+    const uint32_t *__restrict__ codes, uint32_t n, const int32_t *__restrict__ leaf_begin,
+    const int32_t *__restrict__ leaf_end, const int32_t *__restrict__ leaf_level,
+    const uint32_t *__restrict__ leaf_code, const uint32_t *__restrict__ off_f,
+    const uint32_t *__restrict__ off_r, uint32_t nl, uint32_t total, Node *__restrict__ fwd,
+    Node *__restrict__ rev, int32_t *__restrict__ leaf_node_f, int32_t *__restrict__ leaf_node_r,
+    uint32_t node_cap, uint32_t j, int l)
 {
     const int32_t b = leaf_begin[j], e = leaf_end[j];
     const int lev = leaf_level[j];
     const uint32_t code = leaf_code[j];
     const int cl = b > 0 ? common_level(codes[b - 1], code) : -1;
     const int cr = (uint32_t)e < n ? common_level(codes[e - 1], codes[e]) : -1;
+    if (l <= min(cl, cr) || l > lev) return;
+    const bool do_f = l > cl, do_r = l > cr;
     const uint32_t fbase = off_f[j];
     // Backward table: nodes of all later leaves come first.
     const uint32_t rbase = total - off_r[j] - (uint32_t)(lev - cr);
-
-    for (int l = min(cl, cr) + 1; l <= lev; ++l) {
-        const bool do_f = l > cl, do_r = l > cr;
-        Node nd;
-        node_box(code, l, nd);
-        if (l == lev) {
-            nd.begin = b;
-            nd.end = e;
-            nd.leaf = (int32_t)j;
-            const uint32_t fi = fbase + (uint32_t)(l - cl - 1);
-            const uint32_t ri = rbase + (uint32_t)(l - cr - 1);
-            nd.skip = (int32_t)fi + 1;
-            if (fi < node_cap) fwd[fi] = nd;
-            leaf_node_f[j] = (int32_t)fi;
-            nd.skip = (int32_t)ri + 1;
-            if (ri < node_cap) rev[ri] = nd;
-            leaf_node_r[j] = (int32_t)ri;
-            break;
+    Node nd;
+    node_box(code, l, nd);
+    if (l == lev) {
+        nd.begin = b;
+        nd.end = e;
+        nd.leaf = (int32_t)j;
+        const uint32_t fi = fbase + (uint32_t)(l - cl - 1);
+        const uint32_t ri = rbase + (uint32_t)(l - cr - 1);
+        nd.skip = (int32_t)fi + 1;
+        if (fi < node_cap) fwd[fi] = nd;
+        leaf_node_f[j] = (int32_t)fi;
+        nd.skip = (int32_t)ri + 1;
+        if (ri < node_cap) rev[ri] = nd;
+        leaf_node_r[j] = (int32_t)ri;
+        return;
+    }
+    nd.leaf = -1;
+    if (do_f) {
+        const uint32_t hi = gallop_up(leaf_code, j, nl, code, l);
+        const uint32_t fi = fbase + (uint32_t)(l - cl - 1);
+        nd.begin = b;
+        nd.end = hi < nl ? leaf_begin[hi] : (int32_t)n;
+        nd.skip = hi < nl ? (int32_t)off_f[hi] : (int32_t)total;
+        if (fi < node_cap) fwd[fi] = nd;
+    }
+    if (do_r) {
+        const uint32_t lo = gallop_down(leaf_code, j, code, l);
+        const uint32_t ri = rbase + (uint32_t)(l - cr - 1);
+        nd.begin = leaf_begin[lo];
+        nd.end = e;
+        if (lo > 0) {
+            const int32_t pe = leaf_end[lo - 1];
+            const int pcr = common_level(codes[pe - 1], codes[pe]);
+            nd.skip = (int32_t)(total - off_r[lo - 1] - (uint32_t)(leaf_level[lo - 1] - pcr));
+        } else {
+            nd.skip = (int32_t)total;
         }
-        nd.leaf = -1;
-        if (do_f) {
-            const uint32_t hi = gallop_up(leaf_code, j, nl, code, l);
-            const uint32_t fi = fbase + (uint32_t)(l - cl - 1);
-            nd.begin = b;
-            nd.end = hi < nl ? leaf_begin[hi] : (int32_t)n;
-            nd.skip = hi < nl ? (int32_t)off_f[hi] : (int32_t)total;
-            if (fi < node_cap) fwd[fi] = nd;
-        }
-        if (do_r) {
-            const uint32_t lo = gallop_down(leaf_code, j, code, l);
-            const uint32_t ri = rbase + (uint32_t)(l - cr - 1);
-            nd.begin = leaf_begin[lo];
-            nd.end = e;
-            if (lo > 0) {
-                const int32_t pe = leaf_end[lo - 1];
-                const int pcr = common_level(codes[pe - 1], codes[pe]);
-                nd.skip = (int32_t)(total - off_r[lo - 1] - (uint32_t)(leaf_level[lo - 1] - pcr));
-            } else {
-                nd.skip = (int32_t)total;
-            }
-            if (ri < node_cap) rev[ri] = nd;
-        }
+        if (ri < node_cap) rev[ri] = nd;
     }
 }
+
+// Levels 0..16: 17 lanes would be needed for max_level 16 with a level-0
+// leaf; a leaf's levels run from min(cl, cr) + 1 >= 0 to lev <= 16, so each
+// leaf takes a group of 32 lanes (two leaves per wavefront).
+constexpr int kLevelLanes = 32;
 
 __global__ void k_node_emit(const uint32_t *__restrict__ codes, uint32_t n,
                             const int32_t *__restrict__ leaf_begin,
@@ -720,11 +777,58 @@ __global__ void k_node_emit(const uint32_t *__restrict__ codes, uint32_t n,
         if (blockIdx.x == 0 && threadIdx.x == 0) atomicMax(&ctr->bad_nodes, epoch);
         return;
     }
-    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < nl; j += gridDim.x * blockDim.x)
-        emit_leaf_nodes(codes, n, leaf_begin, leaf_end, leaf_level, leaf_code, off_f, off_r, nl,
-                        total, fwd, rev, leaf_node_f, leaf_node_r, node_cap, j);
+    const int l = (int)(threadIdx.x % kLevelLanes);
+    const uint32_t per_block = blockDim.x / kLevelLanes;
+    for (uint32_t j = blockIdx.x * per_block + threadIdx.x / kLevelLanes; j < nl;
+         j += gridDim.x * per_block)
+        emit_leaf_level(codes, n, leaf_begin, leaf_end, leaf_level, leaf_code, off_f, off_r, nl,
+                        total, fwd, rev, leaf_node_f, leaf_node_r, node_cap, j, l);
 }
 
+
+// ---------------------------------------------------------------------------
+// Refit tick (reuse of the last full build's index).  Sec. 4.1 rebuilds the
+// index only when the work of the last tick grows by some factor over recent
+// ticks; between rebuilds, the objects keep their sorted positions and leaves,
+// each record takes the object's new position, and the largest per-axis
+// displacement D of any object since the build is recorded.  Every object of
+// a node's range lay inside the node's quadrant at the build, so it now lies
+// inside the quadrant grown by D on every side; the query kernel prunes with
+// those grown boxes, so results stay exact.
+// ---------------------------------------------------------------------------
+
+__global__ void k_refit(const float *__restrict__ x, const float *__restrict__ y, uint32_t n,
+                        Point *__restrict__ pts, const float2 *__restrict__ anchor,
+                        IndexCounters *__restrict__ ctr, uint32_t epoch)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    float d = 0.0f;
+    if (i < n) {
+        const uint32_t id = pts[i].id;
+        const float px = x[id], py = y[id];
+        const bool ok = (px >= 0.0f) && (px < 1.0f) && (py >= 0.0f) && (py < 1.0f);
+        if (!ok) atomicMax(&ctr->bad_coord, epoch);
+        pts[i].x = px;
+        pts[i].y = py;
+        const float2 a = anchor[i];
+        d = ok ? fmaxf(fabsf(px - a.x), fabsf(py - a.y)) : 0.0f;
+    }
+    // Largest displacement of the wavefront; non-negative floats order like
+    // their bit patterns, so one 64-bit atomicMax keeps the epoch's maximum.
+#pragma unroll
+    for (int s = 1; s < kWave; s <<= 1) d = fmaxf(d, __shfl_xor(d, s, kWave));
+    if ((threadIdx.x & (kWave - 1)) == 0)
+        atomicMax(&ctr->drift, ((unsigned long long)epoch << 32) | __float_as_uint(d));
+}
+
+void launch_refit(IndexBuffers &b, const float *x, const float *y, int64_t n, uint32_t epoch,
+                  hipStream_t s)
+{
+    if (n <= 0) return;
+    const int T = 256;
+    k_refit<<<(uint32_t)((n + T - 1) / T), T, 0, s>>>(x, y, (uint32_t)n, b.pts, b.anchor, b.ctr,
+                                                     epoch);
+}
 
 int64_t node_capacity(int64_t n, int th, int L)
 {
@@ -743,12 +847,12 @@ void launch_build_index(IndexBuffers &b, const float *x, const float *y, int64_t
     const int T = 256;
     const uint32_t g = (uint32_t)((n + T - 1) / T);
     if (n == 0) return;
-    const int64_t words = carve_workspace(b.ws, n, &b.sort, b.scan, 3);
-    k_morton<<<g, T, 0, s>>>(x, y, nn, b.sort.keys[0], b.sort.vals[0], b.ctr, b.ws.base, words,
-                             epoch);
-    const int res = launch_radix_sort(b.sort, n, 2 * kCodeLevels, s);
+    const int64_t words = carve_workspace(b.ws, n, &b.sort, b.scan, 3, &b.ctr->bad_sync_build,
+                                          epoch);
+    k_morton<<<g, T, 0, s>>>(x, y, nn, b.sort.keys[0], b.sort.vals[0], b.xy, b.ctr, b.ws.base,
+                             words, epoch);
+    const int res = launch_radix_sort(b.sort, n, 2 * kCodeLevels, s, b.xy, b.pts, b.anchor);
     const uint32_t *codes = b.sort.keys[res];
-    k_gather<<<g, T, 0, s>>>(codes, b.sort.vals[res], x, y, nn, b.pts);
     k_leaf_flags<<<g, T, 0, s>>>(codes, nn, th, L, b.flags);
     // The exclusive scan goes to the other value buffer; its sum is the leaf
     // count.
@@ -761,7 +865,9 @@ void launch_build_index(IndexBuffers &b, const float *x, const float *y, int64_t
                                 b.leaf_code, b.cnt_f, b.cnt_r, epoch);
     launch_exclusive_scan(b.cnt_f, b.cnt_f, n, b.scan[1], &b.ctr->n_nodes, s, &b.ctr->n_leaves);
     launch_exclusive_scan(b.cnt_r, b.cnt_r, n, b.scan[2], nullptr, s, &b.ctr->n_leaves);
-    k_node_emit<<<gl, T, 0, s>>>(codes, nn, b.leaf_begin, b.leaf_end, b.leaf_level, b.leaf_code,
+    const uint32_t gn = (uint32_t)((n + T / kLevelLanes - 1) / (T / kLevelLanes));
+    k_node_emit<<<gn < 8192 ? gn : 8192, T, 0, s>>>(codes, nn, b.leaf_begin, b.leaf_end,
+                                                   b.leaf_level, b.leaf_code,
                                 b.cnt_f, b.cnt_r, b.ctr, b.fwd, b.rev, b.leaf_node_f,
                                 b.leaf_node_r, (uint32_t)b.node_cap, epoch);
 }

@@ -51,7 +51,13 @@ struct IndexCounters {
     uint32_t bad_nodes;      // build epoch in which the node tables overflowed
     uint32_t bad_issuer;     // query epoch in which an issuer was outside [0,n)
     uint32_t bad_k;          // query epoch in which a k was outside [1,k_max]
+    uint32_t bad_sync_build; // build epoch in which a look-back wait gave up
+    uint32_t bad_sync_query; // query epoch in which a look-back wait gave up
+    uint32_t bad_centre;     // query epoch in which a free centre was outside [0,1)
     uint32_t pad;
+    // (build epoch << 32) | fp32 bits of the largest per-axis displacement of
+    // any object since the last full build, raised by each refit tick.
+    unsigned long long drift;
 };
 
 // Workspace of single-pass scans and radix passes.  Each pass or scan
@@ -61,7 +67,8 @@ struct IndexCounters {
 struct ScanSpace {
     uint64_t *status;   // look-back words, one per tile
     uint32_t *ticket;   // tile ticket counter
-    uint32_t *err;      // set if a look-back wait ever gave up
+    uint32_t *err;      // raised to `epoch` if a look-back wait gives up
+    uint32_t epoch;
 };
 
 // Ping-pong buffers of a radix sort of (key, val) pairs and its workspace.
@@ -72,7 +79,8 @@ struct SortBuffers {
     uint32_t *ghist;    // [kMaxRadixPasses][kRadixBins] global digit counts (zeroed)
     uint64_t *status;   // [passes][tiles][kRadixBins] look-back words (zeroed)
     uint32_t *tickets;  // [kMaxRadixPasses] tile tickets (zeroed)
-    uint32_t *err;
+    uint32_t *err;      // raised to `epoch` if a look-back wait gives up
+    uint32_t epoch;
 };
 
 // A block of workspace words and how a build or a query carves it.
@@ -85,6 +93,8 @@ struct Workspace {
 struct IndexBuffers {
     SortBuffers sort;
     // sorted objects
+    float2 *xy;             // positions interleaved, id order (build staging)
+    float2 *anchor;         // positions at the last full build, sorted order
     Point *pts;
     int32_t *inv;           // sorted position of each object id (built on demand)
     int32_t *leaf_of;       // leaf index of each sorted position
@@ -115,8 +125,10 @@ int64_t workspace_words(int64_t n);
 // Carve a sort workspace (n keys) and `scans` scan workspaces (n values
 // each) from ws; returns the number of words used.  The words must be
 // zeroed before the first pass runs.
+// Carves sort and scan workspace for n items from ws; look-back failures
+// raise *err to epoch.  Returns the words used (all must be zeroed).
 int64_t carve_workspace(const Workspace &ws, int64_t n, SortBuffers *sort, ScanSpace *scans,
-                        int n_scans);
+                        int n_scans, uint32_t *err, uint32_t epoch);
 
 // Zero the first `words` words of a workspace.
 void launch_zero_words(uint64_t *p, int64_t words, hipStream_t s);
@@ -130,7 +142,16 @@ void launch_exclusive_scan(const uint32_t *in, uint32_t *out, int64_t n, const S
 // Stable LSD radix sort of (key, val) pairs by key bits [0, bits) (at most
 // 32); the result ends in keys[res], vals[res] where res is returned.  The
 // workspace in b must be zero (it is consumed).
-int launch_radix_sort(const SortBuffers &b, int64_t n, int bits, hipStream_t s);
+// Sorts (keys, vals) by key; returns the buffer index holding the result.
+// With pts, the last pass writes keys and, instead of vals, the records
+// {xy[val], val, key} to pts (the index build's sorted objects).
+int launch_radix_sort(const SortBuffers &b, int64_t n, int bits, hipStream_t s,
+                      const float2 *xy = nullptr, Point *pts = nullptr,
+                      float2 *anchor = nullptr);
+// Refit tick: new positions into the sorted records of the last full build
+// (same objects, same order, same leaves) and the drift since that build.
+void launch_refit(IndexBuffers &b, const float *x, const float *y, int64_t n, uint32_t epoch,
+                  hipStream_t s);
 
 // Full index build over positions x, y (device, n objects); epoch tags the
 // build's flags (1 .. 2^24-1).

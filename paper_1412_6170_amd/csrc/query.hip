@@ -31,6 +31,8 @@
 // so the kept set is exactly the first k of Definition 1 with id tie-breaks.
 #include <float.h>
 
+#include <utility>
+
 #include "mknn_internal.hpp"
 #include "query.hpp"
 
@@ -49,13 +51,21 @@ constexpr uint64_t kKeyMax = 0x7fefffffffffffffull;
 
 __device__ __forceinline__ double as_f64(uint64_t k) { return __longlong_as_double((long long)k); }
 __device__ __forceinline__ uint64_t as_key(double d) { return (uint64_t)__double_as_longlong(d); }
+// v_min_f64 / v_max_f64 written directly: fmin/fmax on loaded or
+// bit-assembled doubles make the compiler quiet possible signalling NaNs
+// first (one more fp64 op per operand), and keys are never NaN (their
+// exponent field is at most 0x7f7).
 __device__ __forceinline__ uint64_t key_min(uint64_t a, uint64_t b)
 {
-    return as_key(__builtin_fmin(as_f64(a), as_f64(b)));
+    double r;
+    asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(as_f64(a)), "v"(as_f64(b)));
+    return as_key(r);
 }
 __device__ __forceinline__ uint64_t key_max(uint64_t a, uint64_t b)
 {
-    return as_key(__builtin_fmax(as_f64(a), as_f64(b)));
+    double r;
+    asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(as_f64(a)), "v"(as_f64(b)));
+    return as_key(r);
 }
 __device__ __forceinline__ bool key_less(uint64_t a, uint64_t b) { return as_f64(a) < as_f64(b); }
 
@@ -71,10 +81,14 @@ __device__ __forceinline__ float sq_dist(float qx, float qy, float px, float py)
     return ax + ay;
 }
 
-__device__ __forceinline__ float box_lower_bound(float qx, float qy, const Node &nd)
+// Lower bound of d2 over the node's box grown by pad on every side (pad is 0
+// right after a full build; after refit ticks it covers the objects' drift).
+__device__ __forceinline__ float box_lower_bound(float qx, float qy, const Node &nd, float pad)
 {
-    const float gx = (qx < nd.x0) ? (nd.x0 - qx) : ((qx >= nd.x1) ? (qx - nd.x1) : 0.0f);
-    const float gy = (qy < nd.y0) ? (nd.y0 - qy) : ((qy >= nd.y1) ? (qy - nd.y1) : 0.0f);
+    const float x0 = nd.x0 - pad, x1 = nd.x1 + pad;
+    const float y0 = nd.y0 - pad, y1 = nd.y1 + pad;
+    const float gx = (qx < x0) ? (x0 - qx) : ((qx >= x1) ? (qx - x1) : 0.0f);
+    const float gy = (qy < y0) ? (y0 - qy) : ((qy >= y1) ? (qy - y1) : 0.0f);
     const float ax = gx * gx;
     const float ay = gy * gy;
     return ax + ay;
@@ -90,37 +104,66 @@ __device__ __forceinline__ void cmp_swap(uint64_t &lo, uint64_t &hi)
     lo = t;
 }
 
-// Bitonic sorting network on a register array (all indices static).
-template <int N>
-__device__ __forceinline__ void bitonic_sort(uint64_t (&b)[N])
+// Sorting networks on register arrays.  They are expanded with templates
+// (fold expressions over the element indices) rather than unrolled loops, so
+// every index is a compile-time constant whatever the size: an array
+// indexed at run time would be moved to scratch memory.
+
+// One compare-exchange of a bitonic sort stage: blocks of SIZE elements,
+// partner at distance STRIDE, ascending blocks where (I & SIZE) == 0.
+template <int N, int SIZE, int STRIDE, int I>
+__device__ __forceinline__ void sort_ce(uint64_t (&b)[N])
 {
-#pragma unroll
-    for (int size = 2; size <= N; size <<= 1) {
-#pragma unroll
-        for (int stride = size / 2; stride > 0; stride >>= 1) {
-#pragma unroll
-            for (int i = 0; i < N; ++i) {
-                const int j = i ^ stride;
-                if (j > i) {
-                    if ((i & size) == 0) cmp_swap(b[i], b[j]);
-                    else cmp_swap(b[j], b[i]);
-                }
-            }
-        }
+    constexpr int J = I ^ STRIDE;
+    if constexpr (J > I) {
+        if constexpr ((I & SIZE) == 0) cmp_swap(b[I], b[J]);
+        else cmp_swap(b[J], b[I]);
     }
 }
 
+template <int N, int SIZE, int STRIDE, int... I>
+__device__ __forceinline__ void sort_stage(uint64_t (&b)[N], std::integer_sequence<int, I...>)
+{
+    (sort_ce<N, SIZE, STRIDE, I>(b), ...);
+}
+
+template <int N, int SIZE, int STRIDE>
+__device__ __forceinline__ void sort_strides(uint64_t (&b)[N])
+{
+    sort_stage<N, SIZE, STRIDE>(b, std::make_integer_sequence<int, N>{});
+    if constexpr (STRIDE > 1) sort_strides<N, SIZE, STRIDE / 2>(b);
+}
+
+// Bitonic sorting network, ascending.
+template <int N, int SIZE = 2>
+__device__ __forceinline__ void bitonic_sort(uint64_t (&b)[N])
+{
+    if constexpr (SIZE <= N) {
+        sort_strides<N, SIZE, SIZE / 2>(b);
+        bitonic_sort<N, SIZE * 2>(b);
+    }
+}
+
+template <int N, int STRIDE, int I>
+__device__ __forceinline__ void merge_ce(uint64_t (&a)[N])
+{
+    constexpr int J = I ^ STRIDE;
+    if constexpr (J > I) cmp_swap(a[I], a[J]);
+}
+
+template <int N, int STRIDE, int... I>
+__device__ __forceinline__ void merge_stage(uint64_t (&a)[N], std::integer_sequence<int, I...>)
+{
+    (merge_ce<N, STRIDE, I>(a), ...);
+}
+
 // Sort a bitonic register array ascending (half-cleaner cascade).
-template <int N>
+template <int N, int STRIDE = N / 2>
 __device__ __forceinline__ void bitonic_merge(uint64_t (&a)[N])
 {
-#pragma unroll
-    for (int stride = N / 2; stride > 0; stride >>= 1) {
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-            const int j = i ^ stride;
-            if (j > i) cmp_swap(a[i], a[j]);
-        }
+    if constexpr (STRIDE > 0) {
+        merge_stage<N, STRIDE>(a, std::make_integer_sequence<int, N>{});
+        bitonic_merge<N, STRIDE / 2>(a);
     }
 }
 
@@ -142,8 +185,8 @@ __device__ __forceinline__ void bitonic_merge(uint64_t (&a)[N])
 // exceeded by the k-th key (the k-th smallest key of any k other objects
 // bounds it from above), so filtering with it drops nothing that belongs to
 // the answer.  Between merges the threshold may be stale, which only lets
-// more keys into the queue.  The query's own object is queued like any
-// other candidate (its key is (0, own id)) and is removed at merge time.
+// more keys into the queue.  The excluded object (the issuer of the query)
+// is queued like any other candidate and removed by id at merge time.
 template <int K, int P>
 struct Selector {
     uint64_t a[K];
@@ -151,9 +194,9 @@ struct Selector {
     uint32_t cnt;
     uint64_t cap;      // upper bound (exclusive) from the seed
     uint64_t thr;      // min(a[K-1], cap) at the last merge
-    uint64_t self_key;
+    uint32_t excl;     // id of the excluded object (the issuer), or kNoExclude
 
-    __device__ __forceinline__ void init(int k, lds_u64 *lane_queue, uint32_t self_id)
+    __device__ __forceinline__ void init(int k, lds_u64 *lane_queue, uint32_t excl_id)
     {
 #pragma unroll
         for (int s = 0; s < K; ++s) a[s] = (s < K - k) ? 0ull : kKeyMax;
@@ -161,7 +204,7 @@ struct Selector {
         cnt = 0;
         cap = kKeyMax;
         thr = kKeyMax;
-        self_key = (uint64_t)self_id;  // d2 of the query to itself is +0
+        excl = excl_id;
     }
 
     __device__ __forceinline__ void set_cap(uint64_t c)
@@ -187,7 +230,8 @@ struct Selector {
 #pragma unroll
         for (int s = 0; s < P; ++s) b[s] = vq[s * kWave];
 #pragma unroll
-        for (int s = 0; s < P; ++s) b[s] = ((uint32_t)s < cnt && b[s] != self_key) ? b[s] : kKeyMax;
+        for (int s = 0; s < P; ++s)
+            b[s] = ((uint32_t)s < cnt && (uint32_t)b[s] != excl) ? b[s] : kKeyMax;
         bitonic_sort<P>(b);
 #pragma unroll
         for (int i = K - P; i < K; ++i) a[i] = key_min(a[i], b[K - 1 - i]);
@@ -200,6 +244,7 @@ struct Selector {
 template <int K, int P>
 struct Lane {
     float qx, qy;
+    float pad;   // growth of every node box (drift since the last full build)
     bool active;
     Selector<K, P> sel;
     uint32_t n_cand = 0, n_merge = 0, n_node = 0, n_leaf = 0;  // wave-uniform
@@ -254,7 +299,7 @@ struct Lane {
     __device__ __forceinline__ bool wants(const Node &nd) const
     {
         return active &&
-               __float_as_uint(box_lower_bound(qx, qy, nd)) <= (uint32_t)(sel.thr >> 32);
+               __float_as_uint(box_lower_bound(qx, qy, nd, pad)) <= (uint32_t)(sel.thr >> 32);
     }
 };
 
@@ -283,52 +328,100 @@ __device__ __forceinline__ int32_t walk_step(Lane<K, P> &ln, const Node *__restr
     return total;
 }
 
-template <int K, int P>
-__global__ __launch_bounds__(256) void k_knn_tiles(QueryArgs qa)
+// One wavefront per workgroup, so a finished wavefront frees its registers
+// and LDS at once instead of waiting for the slowest wavefront of a larger
+// group (wavefront run times differ several-fold between dense and sparse
+// regions).
+//
+// Tile order is XCD-aware: workgroups are dealt round-robin to the 8 XCDs
+// (workgroup b runs on XCD b mod 8), so workgroup b takes tile
+// (b mod 8) * (groups / 8) + b / 8.  Each XCD then works through one
+// contiguous eighth of the Morton-ordered queries, whose candidates are
+// spatially close and stay in that XCD's L2.  The grid is a multiple of 8;
+// tiles past the last query exit at once.
+constexpr uint32_t kXcds = 8;
+
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t groups)
 {
-    __shared__ uint64_t s_queue[256 / kWave][P * kWave];
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wib = threadIdx.x / kWave;
-    const uint32_t tile = blockIdx.x * (blockDim.x / kWave) + wib;
+    return (b % kXcds) * (groups / kXcds) + b / kXcds;
+}
+
+template <int K, int P>
+__global__ __launch_bounds__(kWave) void k_knn_tiles(QueryArgs qa)
+{
+    __shared__ uint64_t s_queue[P * kWave];
+    const int lane = threadIdx.x;
+    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const uint32_t t = tile * kWave + lane;
     if (tile * kWave >= qa.nq) return;  // whole wavefront idle
 
     Lane<K, P> ln;
     ln.active = t < qa.nq;
+    // After refit ticks the objects have moved by up to D per axis since the
+    // quadrant boxes were made; grow the boxes by D plus a margin that covers
+    // the rounding of D and of the grown edges (2^-23 > 2 * 2^-25, the
+    // largest rounding error of a difference or a sum below 1).
+    ln.pad = 0.0f;
+    {
+        const unsigned long long dw = qa.ctr->drift;
+        const float d = __uint_as_float((uint32_t)dw);
+        if ((uint32_t)(dw >> 32) == qa.build_epoch && d > 0.0f) ln.pad = d + 0x1p-23f;
+    }
     const uint32_t tq = ln.active ? t : qa.nq - 1;
-    const int32_t qp = qa.qpos ? qa.qpos[tq] : (int32_t)tq;
-    const Point q = qa.pts[qp];
-    ln.qx = q.x;
-    ln.qy = q.y;
-    const int32_t row = qa.qrow ? qa.qrow[tq] : (int32_t)q.id;
+    // Query centre, excluded object and sorted position to start from: an
+    // object's own position and id, or a free centre's insertion position.
+    int32_t qp, row;
+    uint32_t excl;
+    if (qa.qpts) {
+        const QPoint c = qa.qpts[tq];
+        ln.qx = c.x;
+        ln.qy = c.y;
+        excl = c.excl;
+        qp = min(max(c.pos, 0), (int32_t)qa.n - 1);
+        row = qa.qrow[tq];
+    } else {
+        qp = qa.qpos ? qa.qpos[tq] : (int32_t)tq;
+        const Point q = qa.pts[qp];
+        ln.qx = q.x;
+        ln.qy = q.y;
+        excl = q.id;
+        row = qa.qrow ? qa.qrow[tq] : (int32_t)q.id;
+    }
     int kq = qa.ks ? qa.ks[row] : qa.k_uniform;
     kq = kq < 1 ? 1 : (kq > K ? K : kq);
-    ln.sel.init(kq, (lds_u64 *)&s_queue[wib][lane], q.id);
+    ln.sel.init(kq, (lds_u64 *)&s_queue[lane], excl);
 
-    // Seed: the kq objects around the query in Morton order (a window of
-    // kq + 1 sorted positions holding the query) are kq other objects, so
-    // the largest of their keys bounds the k-th key from above.  Inactive
-    // lanes keep a zero threshold and never queue anything.
+    // Seed: a window of kq + 1 sorted positions around qp holds at least kq
+    // objects other than the excluded one, so the largest of their keys
+    // bounds the k-th key from above.  Inactive lanes keep a zero threshold
+    // and never queue anything.
     {
         const int32_t n = (int32_t)qa.n;
         uint64_t seed = 0;
         if (n - 1 >= kq) {
             int32_t w0 = qp - kq / 2;
             w0 = w0 < 0 ? 0 : (w0 > n - 1 - kq ? n - 1 - kq : w0);
-#pragma unroll 4
-            for (int s = 0; s <= K; ++s) {
-                if (s <= kq) {
-                    const int32_t j = w0 + s;
-                    if (j != qp) {
-                        const Point p = qa.pts[j];
-                        const float d2 = sq_dist(q.x, q.y, p.x, p.y);
-                        seed = key_max(seed, ((uint64_t)__float_as_uint(d2) << 32) | p.id);
-                    }
-                }
+            // Branch-free: lanes past their window re-read its first object
+            // and contribute a zero key.  K is a multiple of 4: four loads
+            // in flight per step; position K follows the loop.
+            auto seed_step = [&](int s) {
+                const bool in = s <= kq;
+                const Point p = qa.pts[w0 + (in ? s : 0)];
+                const float d2 = sq_dist(ln.qx, ln.qy, p.x, p.y);
+                const uint64_t key = ((uint64_t)__float_as_uint(d2) << 32) | p.id;
+                seed = key_max(seed, (in && p.id != excl) ? key : 0ull);
+            };
+#pragma nounroll
+            for (int s = 0; s < K; s += 4) {
+                seed_step(s);
+                seed_step(s + 1);
+                seed_step(s + 2);
+                seed_step(s + 3);
             }
+            seed_step(K);
             ln.sel.set_cap(seed + 1);
         }
-        if (!ln.active) ln.sel.set_cap(0);
+        ln.sel.set_cap(ln.active ? ln.sel.cap : 0ull);
     }
 
     // Own leaves of the wavefront's queries: a contiguous run of leaves.
@@ -380,18 +473,133 @@ __global__ __launch_bounds__(256) void k_knn_tiles(QueryArgs qa)
     int32_t *__restrict__ oi = qa.out_ids + off;
     float *__restrict__ od = qa.out_d2 + off;
     int cnt = 0;
+    if (kq == K && (off & 3) == 0) {
+        // Full-width row starting on a 16-byte boundary: 16-byte stores, so
+        // each 128-byte line of the row is written by a few consecutive
+        // stores of the lane instead of K separate 4-byte ones.
 #pragma unroll
-    for (int s = 0; s < K; ++s) {
-        const int slot = s - (K - kq);
-        if (slot >= 0) {
-            const uint64_t v = ln.sel.a[s];
-            const bool real = v != kKeyMax;
-            oi[slot] = real ? (int32_t)(uint32_t)v : -1;
-            od[slot] = real ? __uint_as_float((uint32_t)(v >> 32)) : __builtin_inff();
-            cnt += real ? 1 : 0;
+        for (int s = 0; s < K; s += 4) {
+            int4 vi;
+            float4 vd;
+            int32_t *pi = &vi.x;
+            float *pd = &vd.x;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint64_t v = ln.sel.a[s + u];
+                const bool real = v != kKeyMax;
+                pi[u] = real ? (int32_t)(uint32_t)v : -1;
+                pd[u] = real ? __uint_as_float((uint32_t)(v >> 32)) : __builtin_inff();
+                cnt += real ? 1 : 0;
+            }
+            *reinterpret_cast<int4 *>(oi + s) = vi;
+            *reinterpret_cast<float4 *>(od + s) = vd;
+        }
+    } else {
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+            const int slot = s - (K - kq);
+            if (slot >= 0) {
+                const uint64_t v = ln.sel.a[s];
+                const bool real = v != kKeyMax;
+                oi[slot] = real ? (int32_t)(uint32_t)v : -1;
+                od[slot] = real ? __uint_as_float((uint32_t)(v >> 32)) : __builtin_inff();
+                cnt += real ? 1 : 0;
+            }
         }
     }
     qa.out_cnt[row] = cnt;
+}
+
+// ---------------------------------------------------------------------------
+// Free-centre queries (Definition 1: q = (x, y, k) with any centre): the
+// centres are validated and given level-16 Morton codes, sorted by code with
+// the query radix sort, then each is placed among the sorted objects (the
+// position its code would take), which gives the wavefront's starting leaf
+// and the seed window.  Any starting position is correct -- the two walks
+// reach every leaf outside the swept ones -- the code order only keeps the
+// wavefront's queries and candidates close together.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint32_t spread16(uint32_t v)
+{
+    v &= 0x0000ffffu;
+    v = (v | (v << 8)) & 0x00ff00ffu;
+    v = (v | (v << 4)) & 0x0f0f0f0fu;
+    v = (v | (v << 2)) & 0x33333333u;
+    v = (v | (v << 1)) & 0x55555555u;
+    return v;
+}
+
+__global__ void k_point_keys(const float *__restrict__ qx, const float *__restrict__ qy,
+                             const int32_t *__restrict__ exclude, const int32_t *__restrict__ ks,
+                             uint32_t nq, uint32_t n, int k_max, uint32_t *__restrict__ keys,
+                             uint32_t *__restrict__ vals, uint32_t *__restrict__ kcount,
+                             IndexCounters *__restrict__ ctr, uint64_t *__restrict__ ws,
+                             int64_t ws_words, uint32_t epoch)
+{
+    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t w = q; w < ws_words; w += (int64_t)gridDim.x * blockDim.x) ws[w] = 0ull;
+    if (q >= nq) return;
+    const float px = qx[q], py = qy[q];
+    const bool ok = (px >= 0.0f) && (px < 1.0f) && (py >= 0.0f) && (py < 1.0f);
+    if (!ok) atomicMax(&ctr->bad_centre, epoch);
+    const uint32_t cx = min(ok ? (uint32_t)(px * 65536.0f) : 0u, 65535u);
+    const uint32_t cy = min(ok ? (uint32_t)(py * 65536.0f) : 0u, 65535u);
+    keys[q] = spread16(cx) | (spread16(cy) << 1);
+    vals[q] = q;
+    if (exclude) {
+        const int32_t e = exclude[q];
+        if (e < -1 || e >= (int32_t)n) atomicMax(&ctr->bad_issuer, epoch);
+    }
+    if (ks) {
+        const int32_t k = ks[q];
+        const bool kok = k >= 1 && k <= k_max;
+        if (!kok) atomicMax(&ctr->bad_k, epoch);
+        kcount[q] = kok ? (uint32_t)k : 1u;
+    }
+}
+
+__global__ void k_point_place(const uint32_t *__restrict__ codes, const uint32_t *__restrict__ rows,
+                              uint32_t nq, const float *__restrict__ qx,
+                              const float *__restrict__ qy, const int32_t *__restrict__ exclude,
+                              const Point *__restrict__ pts, uint32_t n,
+                              QPoint *__restrict__ qpts)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nq) return;
+    const uint32_t q = rows[i], code = codes[i];
+    // First sorted object whose code is not below the centre's code.
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (pts[mid].code < code) lo = mid + 1;
+        else hi = mid;
+    }
+    QPoint c;
+    c.x = qx[q];
+    c.y = qy[q];
+    const int32_t e = exclude ? exclude[q] : -1;
+    c.excl = (e >= 0 && e < (int32_t)n) ? (uint32_t)e : kNoExclude;
+    c.pos = (int32_t)lo;
+    qpts[i] = c;
+}
+
+void launch_point_prep(const PointPrep &p, hipStream_t s)
+{
+    const int T = 256;
+    if (p.nq == 0) return;
+    k_point_keys<<<(p.nq + T - 1) / T, T, 0, s>>>(p.qx, p.qy, p.exclude, p.ks, p.nq, p.n, p.k_max,
+                                                 p.sort.keys[0], p.sort.vals[0], p.kcount, p.ctr,
+                                                 p.ws, p.ws_words, p.epoch);
+}
+
+void launch_point_place(const uint32_t *codes, const uint32_t *rows, uint32_t nq, const float *qx,
+                        const float *qy, const int32_t *exclude, const Point *pts, uint32_t n,
+                        QPoint *qpts, hipStream_t s)
+{
+    const int T = 256;
+    if (nq == 0) return;
+    k_point_place<<<(nq + T - 1) / T, T, 0, s>>>(codes, rows, nq, qx, qy, exclude, pts, n, qpts);
 }
 
 int k_class(int k)
@@ -407,9 +615,8 @@ void launch_knn(const QueryArgs &qa, int kclass, hipStream_t s)
 {
     if (qa.nq == 0) return;
     const uint32_t tiles = (qa.nq + kWave - 1) / kWave;
-    const uint32_t waves_per_block = 4;
-    const uint32_t blocks = (tiles + waves_per_block - 1) / waves_per_block;
-    const dim3 grid(blocks), block(waves_per_block * kWave);
+    const uint32_t groups = (tiles + kXcds - 1) / kXcds * kXcds;
+    const dim3 grid(groups), block(kWave);
     switch (kclass) {
     case 8: k_knn_tiles<8, 8><<<grid, block, 0, s>>>(qa); break;
     case 16: k_knn_tiles<16, 16><<<grid, block, 0, s>>>(qa); break;

@@ -5,6 +5,16 @@
 
 namespace mknn {
 
+// A free query centre in processing (Morton) order: its position, the id of
+// the object it excludes (kNoExclude: none) and its insertion position among
+// the sorted objects (where its code would sort).
+constexpr uint32_t kNoExclude = 0xffffffffu;
+struct __align__(16) QPoint {
+    float x, y;
+    uint32_t excl;
+    int32_t pos;
+};
+
 struct QueryArgs {
     const Point *pts;            // sorted objects
     uint32_t n;                  // number of objects
@@ -18,6 +28,8 @@ struct QueryArgs {
                                  // processing order; null = identity
     const int32_t *qrow;         // result row of each query, processing
                                  // order; null = object id (every object queries)
+    const QPoint *qpts;          // free centres in processing order (then qpos
+                                 // is unused); null = queries issued by objects
     uint32_t nq;
     const int32_t *ks;           // k per result row (range-checked); null = k_uniform
     int32_t k_uniform;
@@ -25,6 +37,7 @@ struct QueryArgs {
     int32_t *out_ids;
     float *out_d2;
     int32_t *out_cnt;
+    uint32_t build_epoch;        // epoch of the current index (refit drift tag)
     unsigned long long *counters;  // null, or [candidate steps, merges,
                                    // node visits, leaf sweeps, wavefronts]
 };
@@ -43,7 +56,27 @@ struct QueryPrep {
     uint32_t epoch;              // query epoch for the error flags
 };
 
+// Free-centre queries: validate and encode the centres, then (after the
+// query sort by code) place each one among the sorted objects.
+struct PointPrep {
+    const float *qx, *qy;        // device, nq entries
+    const int32_t *exclude;      // device, nq entries (-1: none), or null
+    const int32_t *ks;           // device, nq entries, or null
+    uint32_t nq, n;
+    int k_max;
+    SortBuffers sort;            // keys[0]/vals[0] receive (code, query)
+    uint32_t *kcount;
+    IndexCounters *ctr;
+    uint64_t *ws;
+    int64_t ws_words;
+    uint32_t epoch;
+};
+
 int k_class(int k);
+void launch_point_prep(const PointPrep &p, hipStream_t s);
+void launch_point_place(const uint32_t *codes, const uint32_t *rows, uint32_t nq, const float *qx,
+                        const float *qy, const int32_t *exclude, const Point *pts, uint32_t n,
+                        QPoint *qpts, hipStream_t s);
 void launch_knn(const QueryArgs &qa, int kclass, hipStream_t s);
 void launch_query_prep(const QueryPrep &p, hipStream_t s);
 void launch_offsets(const uint32_t *kcount, uint32_t nq, uint32_t *scan_out, const ScanSpace &sp,

@@ -1,0 +1,119 @@
+"""GPU: index reuse across ticks (refit ticks).  The objects keep the last
+full build's order, leaves and node tables; queries prune with node boxes
+grown by the objects' drift, and must still return exactly the oracle's
+answer on the current positions."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1412_6170_amd import binding, workloads
+from tests.helpers import family, f32
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    torch.cuda.set_device(0)
+    yield
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def same_bits(a, b):
+    return np.array_equal(np.asarray(a, np.float32).view(np.uint32),
+                          np.asarray(b, np.float32).view(np.uint32))
+
+
+def check(got, exp):
+    assert np.array_equal(got[2], exp[2])
+    assert np.array_equal(got[0], exp[0]) and same_bits(got[1], exp[1])
+
+
+def test_refit_ticks_moving_clusters():
+    w = workloads.clustered_1m(n=200_000, ticks=6)
+    k = 32
+    with binding.Context(w.n, w.n, k, leaf_capacity=32) as c:
+        for t in range(w.ticks):
+            x, y, _, _, _ = w.tick(t)
+            say("refit clustered_200k tick %d" % t)
+            c.load_positions(torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda())
+            if t == 0:
+                c.advance_tick()
+            else:
+                c.refit_tick()
+            c.query(k=k)
+            got = c.fetch()
+            st = c.stats()
+            assert st["refits"] == t
+            assert (st["drift"] > 0) == (t > 0)
+            check(got, oracle.knn(x, y, k=k, th=32, threads=16))
+
+
+def test_refit_after_large_moves_and_all_query_kinds():
+    x0, y0 = family("clustered", 20_000, 3)
+    rng = np.random.default_rng(5)
+    with binding.Context(len(x0), len(x0), 24, leaf_capacity=16) as c:
+        c.load_positions(x0, y0)
+        c.advance_tick()
+        for step in range(3):
+            # A tenth of the objects jump anywhere; the rest jitter.
+            x, y = x0.copy(), y0.copy()
+            jump = rng.random(len(x)) < 0.1
+            x[jump] = rng.random(jump.sum(), dtype=np.float32)
+            y[jump] = rng.random(jump.sum(), dtype=np.float32)
+            x = f32(np.clip(x + rng.uniform(-1e-3, 1e-3, len(x)), 0, 1 - 2 ** -24))
+            y = f32(np.clip(y + rng.uniform(-1e-3, 1e-3, len(y)), 0, 1 - 2 ** -24))
+            say("refit large moves step %d" % step)
+            c.load_positions(x, y)
+            c.refit_tick()
+            c.query(k=24)
+            check(c.fetch(), oracle.brute_knn(x, y, k=24, threads=16))
+            iss = rng.integers(0, len(x), 3000).astype(np.int32)
+            ks = rng.integers(1, 25, 3000).astype(np.int32)
+            c.query(issuers=iss, ks=ks)
+            g = c.fetch()
+            e = oracle.brute_knn(x, y, issuers=iss, ks=ks, threads=16)
+            assert np.array_equal(g[3], e[3])
+            check(g, e)
+            qx = rng.random(2000, dtype=np.float32)
+            qy = rng.random(2000, dtype=np.float32)
+            c.query_points(qx, qy, k=7)
+            check(c.fetch(), oracle.brute_knn_points(x, y, qx, qy, k=7, threads=16))
+
+
+def test_refit_state_errors():
+    x, y = family("uniform", 300, 1)
+    with binding.Context(400, 400, 8) as c:
+        c.load_positions(x, y)
+        with pytest.raises(binding.MknnError) as e:
+            c.refit_tick()
+        assert e.value.code == -3
+        c.advance_tick()
+        c.load_positions(f32(np.append(x, 0.5)), f32(np.append(y, 0.5)))
+        with pytest.raises(binding.MknnError) as e:
+            c.refit_tick()
+        assert e.value.code == -3
+        c.load_positions(x, y)
+        c.refit_tick()
+        c.query(k=8)
+        check(c.fetch(), oracle.brute_knn(x, y, k=8))
+
+
+def test_reuse_policy_stays_exact():
+    w = workloads.clustered_1m(n=100_000, ticks=8)
+    pol = binding.ReusePolicy(factor=1.5)
+    kinds = []
+    with binding.Context(w.n, w.n, 16, leaf_capacity=16, timing=True) as c:
+        for t in range(w.ticks):
+            x, y, _, _, _ = w.tick(t)
+            kinds.append(pol.tick(c, x, y))
+            c.query(k=16)
+            check(c.fetch(), oracle.knn(x, y, k=16, th=16, threads=16))
+    say("policy ticks:", kinds)
+    assert kinds[0] == "build" and "refit" in kinds

@@ -1,0 +1,47 @@
+"""CPU: the HIP kernels compile for gfx950 with no scratch (private) memory
+and within the register budget their launch shapes assume.  A register
+array indexed at run time, or a sorting network the compiler failed to
+expand, shows up as scratch use long before it shows up as a slowdown."""
+import os
+import re
+import shutil
+import subprocess
+
+import pytest
+
+from paper_1412_6170_amd import build
+
+pytestmark = pytest.mark.skipif(not os.path.exists(build.HIPCC) and not shutil.which("hipcc"),
+                                reason="hipcc not available")
+
+
+def kernel_descriptors(src, tmp_path):
+    out = tmp_path / (os.path.basename(src) + ".s")
+    flags = [f for f in build.FLAGS if f not in ("-shared", "-fPIC")]
+    subprocess.run([build.HIPCC] + flags + ["--offload-device-only", "-S", "-o", str(out), src],
+                   check=True, capture_output=True)
+    text = out.read_text()
+    kds = {}
+    for m in re.finditer(r"\.amdhsa_kernel (\S+)(.*?)\.end_amdhsa_kernel", text, re.S):
+        body = m.group(2)
+        get = lambda key: int(re.search(r"\.%s (\d+)" % key, body).group(1))
+        kds[m.group(1)] = {"scratch": get("amdhsa_private_segment_fixed_size"),
+                           "vgpr": get("amdhsa_next_free_vgpr")}
+    return kds
+
+
+@pytest.mark.parametrize("name", ["index.hip", "query.hip"])
+def test_no_scratch(name, tmp_path):
+    kds = kernel_descriptors(os.path.join(build.HERE, "csrc", name), tmp_path)
+    assert kds, "no kernels found"
+    bad = {k: v for k, v in kds.items() if v["scratch"] != 0}
+    assert not bad, bad
+
+
+def test_query_kernel_register_budget(tmp_path):
+    kds = kernel_descriptors(os.path.join(build.HERE, "csrc", "query.hip"), tmp_path)
+    knn = {k: v for k, v in kds.items() if "k_knn_tiles" in k}
+    assert len(knn) == 5
+    # K = 32 (the benchmark's k) must keep 4 wavefronts per SIMD.
+    k32 = [v for k, v in knn.items() if "ILi32ELi16E" in k][0]
+    assert k32["vgpr"] <= 128, k32
