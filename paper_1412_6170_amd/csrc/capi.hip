@@ -178,7 +178,6 @@ void for_each_buffer(mknn_ctx *c, F &&f)
     f(c->ix.pts, N);
     f(c->ix.inv, N);
     f(c->ix.leaf_of, N);
-    f(c->ix.flags, N);
     f(c->ix.leaf_begin, N);
     f(c->ix.leaf_end, N);
     f(c->ix.leaf_level, N);

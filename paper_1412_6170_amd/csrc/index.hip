@@ -7,9 +7,10 @@
 //                    staged in LDS and written back in digit runs; the
 //                    last pass writes the sorted objects as 16-byte records
 //                    {x, y, id, code}
-//   k_leaf_flags     which adjacent sorted objects fall in different leaves
-//   k_leaf_emit      leaf ranges from the flags' exclusive scan
-//   k_leaf_info      leaf level and the node count each leaf contributes
+//   k_leaves         which adjacent sorted objects fall in different leaves,
+//                    scanned in the same pass into leaf ranges
+//   k_leaf_nodes     leaf level and the node count each leaf contributes,
+//                    scanned in the same pass into node positions
 //   k_node_emit      depth-first node tables (forward and backward) with
 //                    subtree-skip links, for stackless Morton-order walks
 //
@@ -143,7 +144,7 @@ __device__ __forceinline__ void lb_publish(uint64_t *status, uint32_t stride, ui
 // flight together), then consumed in order: aggregates are added until an
 // inclusive prefix is met; a word not yet published stops the pass and the
 // next read starts from it.
-constexpr int kLbWindow = 8;
+constexpr int kLbWindow = 16;
 
 __device__ __forceinline__ uint64_t lb_resolve(uint64_t *status, uint32_t stride, uint32_t tile,
                                                uint64_t agg, uint32_t *err, uint32_t epoch)
@@ -188,6 +189,47 @@ __device__ __forceinline__ uint64_t lb_resolve(uint64_t *status, uint32_t stride
     return excl;
 }
 
+// The same for a single look-back word per tile, resolved by one whole
+// wavefront: lane i reads predecessor t - i, so 64 words are read per round.
+// Returns the exclusive prefix in every lane; lane 0 publishes the inclusive
+// prefix.
+__device__ __forceinline__ uint64_t lb_resolve_wave(uint64_t *status, uint32_t tile, uint64_t agg,
+                                                    uint32_t *err, uint32_t epoch)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    uint64_t excl = 0;
+    int64_t t = (int64_t)tile - 1;
+    uint32_t spins = 0;
+    while (t >= 0) {
+        const int64_t mine = t - lane;
+        // Below tile 0, a zero inclusive filler ends the walk.
+        const uint64_t w = mine >= 0 ? lb_load(status + mine) : kLbInc;
+        const uint64_t flag = w & ~kLbVal;
+        const uint64_t inc = __ballot(flag == kLbInc);
+        const uint64_t none = __ballot(flag == 0);
+        const int first_inc = inc ? __builtin_ctzll(inc) : kWave;
+        const int first_none = none ? __builtin_ctzll(none) : kWave;
+        // Lanes [0, take) are consumed this round.
+        const bool done = first_inc < first_none;
+        const int take = done ? first_inc + 1 : first_none;
+        uint64_t v = lane < take ? (w & kLbVal) : 0ull;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) v += __shfl_xor(v, d, kWave);
+        excl += v;
+        if (done) break;
+        t -= take;
+        if (take == 0) {
+            if (++spins > kSpinLimit) {
+                if (lane == 0) atomicMax(err, epoch);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    if (lane == 0) lb_store(status + tile, kLbInc | (excl + agg));
+    return excl;
+}
+
 __device__ __forceinline__ uint32_t take_ticket(uint32_t *ticket)
 {
     __shared__ uint32_t s_ticket;
@@ -222,11 +264,13 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_lb(const uint32_t *in, ui
     }
     uint32_t agg;
     uint32_t pre = block_excl_scan<kScanThreads>(sum, &agg);
-    if (threadIdx.x == 0) {
-        lb_publish(sp.status, 1, tile, agg);
-        const uint64_t e = lb_resolve(sp.status, 1, tile, agg, sp.err, sp.epoch);
-        s_excl = (uint32_t)e;
-        if (total && base + kScanTile >= n) *total = (uint32_t)e + agg;
+    if (threadIdx.x == 0) lb_publish(sp.status, 1, tile, agg);
+    if (threadIdx.x < kWave) {
+        const uint64_t e = lb_resolve_wave(sp.status, tile, agg, sp.err, sp.epoch);
+        if (threadIdx.x == 0) {
+            s_excl = (uint32_t)e;
+            if (total && base + kScanTile >= n) *total = (uint32_t)e + agg;
+        }
     }
     __syncthreads();
     pre += s_excl;
@@ -297,7 +341,7 @@ __global__ void k_morton(const float *__restrict__ x, const float *__restrict__ 
 // Stable LSD radix sort, 8-bit digits, one launch per pass
 //
 // k_radix_ghist counts every pass's digits over all keys in one read (keys
-// do not change between passes, only their order).  Each pass then runs one
+// do not change between passes, only their order), in LDS per workgroup.  Each pass then runs one
 // kernel over tiles of kSortTile keys:
 //   * wavefront w of the tile owns a contiguous quarter of it and ranks its
 //     keys in rounds of 64 in position order; lanes holding the same digit
@@ -312,7 +356,7 @@ __global__ void k_morton(const float *__restrict__ x, const float *__restrict__ 
 //     gather follows.
 // ---------------------------------------------------------------------------
 
-constexpr int kGhistItems = 32;  // keys per thread in the histogram kernel
+constexpr int kGhistItems = 8;  // keys per thread in the histogram kernel
 
 // Lanes of the wavefront (among `valid`) holding the same 8-bit digit d.
 __device__ __forceinline__ uint64_t digit_peers(uint32_t d, uint64_t valid)
@@ -334,22 +378,14 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_ghist(const uint32_t *__
 #pragma unroll
     for (int p = 0; p < kMaxRadixPasses; ++p) s_h[p][threadIdx.x] = 0;
     __syncthreads();
-    const int lane = threadIdx.x & (kWave - 1);
-    const uint64_t lt_mask = (1ull << lane) - 1ull;
     const uint32_t base = blockIdx.x * (uint32_t)(kSortThreads * kGhistItems);
+#pragma unroll
     for (int j = 0; j < kGhistItems; ++j) {
         const uint32_t i = base + j * kSortThreads + threadIdx.x;
-        const bool ok = i < n;
-        const uint64_t valid = __ballot(ok);
-        if (valid == 0ull) break;  // wave-uniform
-        const uint32_t k = ok ? keys[i] : 0u;
-        for (int p = 0; p < passes; ++p) {
-            // One LDS atomic per distinct digit of the wavefront: clustered
-            // codes share their high digits, and same-address atomics
-            // would serialise.
-            const uint32_t d = (k >> (kRadixBits * p)) & (kRadixBins - 1);
-            const uint64_t peers = digit_peers(d, valid);
-            if (ok && (peers & lt_mask) == 0ull) atomicAdd(&s_h[p][d], (uint32_t)__popcll(peers));
+        if (i < n) {
+            const uint32_t k = keys[i];
+            for (int p = 0; p < passes; ++p)
+                atomicAdd(&s_h[p][(k >> (kRadixBits * p)) & (kRadixBins - 1)], 1u);
         }
     }
     __syncthreads();
@@ -539,94 +575,172 @@ void launch_inverse(const IndexBuffers &b, int64_t n, hipStream_t s)
     k_inverse<<<(uint32_t)((n + 255) / 256), 256, 0, s>>>(b.pts, (uint32_t)n, b.inv);
 }
 
-// flags[0] = 1; flags[i+1] = 1 iff sorted objects i and i+1 lie in different
-// leaves, i.e. iff the deepest quadrant holding both (level c) is split:
-// c < L and the quadrant holds more than th objects.  The quadrant is a run
-// [lo, hi] of the sorted codes; it holds more than th objects iff
-// codes[lo + th] still lies in it.  lo is found by a binary search over the
-// last th positions up to i (if the run starts even earlier, the search
-// returns i + 1 - th and the test still holds, since then i + 1 = lo + th).
-__global__ void k_leaf_flags(const uint32_t *__restrict__ codes, uint32_t n, int th, int L,
-                             uint32_t *__restrict__ flags)
+// A new leaf starts at sorted position p iff p = 0 or objects p-1 and p lie
+// in different leaves, i.e. iff the deepest quadrant holding both (level c)
+// is split: c < L and the quadrant holds more than th objects.  The
+// quadrant is a run [lo, hi] of the sorted codes; it holds more than th
+// objects iff codes[lo + th] still lies in it.  lo is found by a binary
+// search over the last th positions up to p-1 (if the run starts even
+// earlier, the search returns p - th and the test still holds, since then
+// p = lo + th).
+//
+// k_leaves does this for kScanItems consecutive positions per thread, with
+// the searches of a thread's positions advancing in lockstep (their loads
+// are independent and in flight together), scans the flags in one pass
+// with decoupled look-back, and writes the leaf of every position and the
+// [begin, end) range of every leaf; the last tile writes the leaf count.
+__global__ __launch_bounds__(kScanThreads) void k_leaves(
+    const uint32_t *__restrict__ codes, uint32_t n, int th, int L, int search_steps, ScanSpace sp,
+    IndexCounters *__restrict__ ctr, int32_t *__restrict__ leaf_of,
+    int32_t *__restrict__ leaf_begin, int32_t *__restrict__ leaf_end)
 {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    if (i == 0) flags[0] = 1u;
-    if (i + 1 >= n) return;
-    const uint32_t a = codes[i], b = codes[i + 1];
-    const int c = common_level(a, b);
-    uint32_t split = 0;
-    if (c < L) {
-        int64_t first = (int64_t)i + 1 - th;
-        if (first < 0) first = 0;
-        int64_t count = (int64_t)i - first;  // positions before i still to test
-        while (count > 0) {
-            const int64_t step = count >> 1;
-            const int64_t mid = first + step;
-            if (!same_quadrant(codes[mid], a, c)) {
-                first = mid + 1;
-                count -= step + 1;
-            } else {
-                count = step;
-            }
-        }
-        const int64_t last = first + th;
-        split = (last < (int64_t)n && same_quadrant(codes[last], a, c)) ? 1u : 0u;
-    }
-    flags[i + 1] = split;
-}
+    __shared__ uint32_t s_excl;
+    const uint32_t tile = take_ticket(sp.ticket);
+    const uint32_t base = tile * (uint32_t)kScanTile;
+    if (base >= n) return;  // past the data; nobody waits on it
+    const uint32_t mine = base + threadIdx.x * (uint32_t)kScanItems;
 
-// From the exclusive scan of the flags: leaf of every sorted object and the
-// [begin, end) range of every leaf.
-__global__ void k_leaf_emit(const uint32_t *__restrict__ flags, const uint32_t *__restrict__ excl,
-                            uint32_t n, int32_t *__restrict__ leaf_of,
-                            int32_t *__restrict__ leaf_begin, int32_t *__restrict__ leaf_end)
-{
-    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    uint32_t f = flags[i];
-    int32_t leaf = (int32_t)(excl[i] + f) - 1;
-    leaf_of[i] = leaf;
-    if (f) {
-        leaf_begin[leaf] = (int32_t)i;
-        if (leaf > 0) leaf_end[leaf - 1] = (int32_t)i;
+    uint32_t a[kScanItems];
+    int c[kScanItems];
+    int64_t first[kScanItems], count[kScanItems];
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        const uint32_t p = mine + j;
+        const bool pair = p >= 1 && p < n;
+        const uint32_t q = pair ? p - 1 : 0;
+        a[j] = codes[q];
+        const uint32_t b = pair ? codes[p] : a[j];
+        c[j] = pair ? common_level(a[j], b) : kCodeLevels;
+        first[j] = (int64_t)q + 1 - th;
+        if (first[j] < 0) first[j] = 0;
+        count[j] = (pair && c[j] < L) ? (int64_t)q - first[j] : 0;
     }
-    if (i + 1 == n) leaf_end[leaf] = (int32_t)n;
+    for (int step = 0; step < search_steps; ++step) {
+#pragma unroll
+        for (int j = 0; j < kScanItems; ++j) {
+            const int64_t half = count[j] >> 1;
+            const int64_t mid = first[j] + half;
+            const bool out = count[j] > 0 && !same_quadrant(codes[mid], a[j], c[j]);
+            first[j] = out ? mid + 1 : first[j];
+            count[j] = count[j] > 0 ? (out ? count[j] - half - 1 : half) : 0;
+        }
+    }
+    uint32_t f[kScanItems], sum = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        const uint32_t p = mine + j;
+        uint32_t split = 0;
+        if (p >= 1 && p < n && c[j] < L) {
+            const int64_t last = first[j] + th;
+            split = (last < (int64_t)n && same_quadrant(codes[last], a[j], c[j])) ? 1u : 0u;
+        }
+        f[j] = p == 0 ? 1u : split;
+        f[j] = p < n ? f[j] : 0u;
+        sum += f[j];
+    }
+    uint32_t agg;
+    uint32_t pre = block_excl_scan<kScanThreads>(sum, &agg);
+    if (threadIdx.x == 0) lb_publish(sp.status, 1, tile, agg);
+    if (threadIdx.x < kWave) {
+        const uint64_t e = lb_resolve_wave(sp.status, tile, agg, sp.err, sp.epoch);
+        if (threadIdx.x == 0) {
+            s_excl = (uint32_t)e;
+            if (base + kScanTile >= n) ctr->n_leaves = (uint32_t)e + agg;
+        }
+    }
+    __syncthreads();
+    pre += s_excl;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        const uint32_t p = mine + j;
+        if (p < n) {
+            pre += f[j];
+            const int32_t leaf = (int32_t)pre - 1;
+            leaf_of[p] = leaf;
+            if (f[j]) {
+                leaf_begin[leaf] = (int32_t)p;
+                if (leaf > 0) leaf_end[leaf - 1] = (int32_t)p;
+            }
+            if (p + 1 == n) leaf_end[leaf] = (int32_t)n;
+        }
+    }
 }
 
 // Leaf level, and the nodes each leaf contributes to the depth-first
 // tables: its inner ancestors below the deepest quadrant it shares with the
-// previous leaf (forward) or next leaf (backward), then itself.
-__global__ void k_leaf_info(const uint32_t *__restrict__ codes, uint32_t n, int th, int L,
-                            const int32_t *__restrict__ leaf_begin,
-                            const int32_t *__restrict__ leaf_end, IndexCounters *__restrict__ ctr,
-                            int32_t *__restrict__ leaf_level, uint32_t *__restrict__ leaf_code,
-                            uint32_t *__restrict__ cnt_f, uint32_t *__restrict__ cnt_r,
-                            uint32_t epoch)
+// previous leaf (forward) or next leaf (backward), then itself.  Both node
+// counts are scanned in the same pass (two look-back chains, resolved by
+// two wavefronts side by side) into the leaves' first node positions; the
+// last tile writes the node count.  Leaves are counted on the device, so
+// the grid covers every position and tiles past the leaves exit.
+__global__ __launch_bounds__(kScanThreads) void k_leaf_nodes(
+    const uint32_t *__restrict__ codes, uint32_t n, int th, int L,
+    const int32_t *__restrict__ leaf_begin, const int32_t *__restrict__ leaf_end, ScanSpace spf,
+    ScanSpace spr, IndexCounters *__restrict__ ctr, int32_t *__restrict__ leaf_level,
+    uint32_t *__restrict__ leaf_code, uint32_t *__restrict__ off_f, uint32_t *__restrict__ off_r,
+    uint32_t epoch)
 {
-    // Grid-stride over the leaves (their count is only known on the device).
+    __shared__ uint32_t s_excl[2];
     const uint32_t nl = ctr->n_leaves;
-    const uint32_t stride = gridDim.x * blockDim.x;
+    const uint32_t tile = take_ticket(spf.ticket);
+    const uint32_t base = tile * (uint32_t)kScanTile;
+    if (base >= nl) return;
+    const uint32_t mine = base + threadIdx.x * (uint32_t)kScanItems;
+    uint32_t cf[kScanItems], cr[kScanItems], sf = 0, sr = 0;
     int deepest = 0;
-    for (uint32_t j0 = blockIdx.x * blockDim.x; j0 < nl; j0 += stride) {
-        const uint32_t j = j0 + threadIdx.x;
-        if (j < nl) {
-            const int32_t b = leaf_begin[j], e = leaf_end[j];
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        const uint32_t p = mine + j;
+        cf[j] = cr[j] = 0;
+        if (p < nl) {
+            const int32_t b = leaf_begin[p], e = leaf_end[p];
             const int cl = b > 0 ? common_level(codes[b - 1], codes[b]) : -1;
-            const int cr = (uint32_t)e < n ? common_level(codes[e - 1], codes[e]) : -1;
-            const int lev = (e - b <= th) ? max(cl, cr) + 1 : L;
-            leaf_level[j] = lev;
-            leaf_code[j] = codes[b];
-            cnt_f[j] = (uint32_t)(lev - cl);
-            cnt_r[j] = (uint32_t)(lev - cr);
+            const int crl = (uint32_t)e < n ? common_level(codes[e - 1], codes[e]) : -1;
+            const int lev = (e - b <= th) ? max(cl, crl) + 1 : L;
+            leaf_level[p] = lev;
+            leaf_code[p] = codes[b];
+            cf[j] = (uint32_t)(lev - cl);
+            cr[j] = (uint32_t)(lev - crl);
             deepest = max(deepest, lev);
         }
+        sf += cf[j];
+        sr += cr[j];
+    }
+    uint32_t agg_f, agg_r;
+    uint32_t pre_f = block_excl_scan<kScanThreads>(sf, &agg_f);
+    __syncthreads();  // the scan's shared partials are reused below
+    uint32_t pre_r = block_excl_scan<kScanThreads>(sr, &agg_r);
+    if (threadIdx.x == 0) {
+        lb_publish(spf.status, 1, tile, agg_f);
+        lb_publish(spr.status, 1, tile, agg_r);
+    }
+    if (threadIdx.x < kWave) {
+        const uint64_t e = lb_resolve_wave(spf.status, tile, agg_f, spf.err, spf.epoch);
+        if (threadIdx.x == 0) {
+            s_excl[0] = (uint32_t)e;
+            if (base + kScanTile >= nl) ctr->n_nodes = (uint32_t)e + agg_f;
+        }
+    } else if (threadIdx.x < 2 * kWave) {
+        const uint64_t e = lb_resolve_wave(spr.status, tile, agg_r, spr.err, spr.epoch);
+        if (threadIdx.x == kWave) s_excl[1] = (uint32_t)e;
+    }
+    __syncthreads();
+    pre_f += s_excl[0];
+    pre_r += s_excl[1];
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        const uint32_t p = mine + j;
+        if (p < nl) {
+            off_f[p] = pre_f;
+            off_r[p] = pre_r;
+        }
+        pre_f += cf[j];
+        pre_r += cr[j];
     }
     // Statistic only: one atomic per wavefront that saw leaves.
 #pragma unroll
     for (int d = 1; d < kWave; d <<= 1) deepest = max(deepest, __shfl_xor(deepest, d, kWave));
-    const uint32_t wave0 = blockIdx.x * blockDim.x + (threadIdx.x & ~(kWave - 1));
-    if ((threadIdx.x & (kWave - 1)) == 0 && wave0 < nl)
+    if ((threadIdx.x & (kWave - 1)) == 0 && deepest > 0)
         atomicMax(&ctr->deepest, (epoch << 8) | (uint32_t)deepest);
 }
 
@@ -801,9 +915,10 @@ __global__ void k_refit(const float *__restrict__ x, const float *__restrict__ y
                         Point *__restrict__ pts, const float2 *__restrict__ anchor,
                         IndexCounters *__restrict__ ctr, uint32_t epoch)
 {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    // A fixed grid strides over the objects, so few workgroups reach the
+    // shared maximum below.
     float d = 0.0f;
-    if (i < n) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const uint32_t id = pts[i].id;
         const float px = x[id], py = y[id];
         const bool ok = (px >= 0.0f) && (px < 1.0f) && (py >= 0.0f) && (py < 1.0f);
@@ -811,14 +926,24 @@ __global__ void k_refit(const float *__restrict__ x, const float *__restrict__ y
         pts[i].x = px;
         pts[i].y = py;
         const float2 a = anchor[i];
-        d = ok ? fmaxf(fabsf(px - a.x), fabsf(py - a.y)) : 0.0f;
+        d = fmaxf(d, ok ? fmaxf(fabsf(px - a.x), fabsf(py - a.y)) : 0.0f);
     }
-    // Largest displacement of the wavefront; non-negative floats order like
-    // their bit patterns, so one 64-bit atomicMax keeps the epoch's maximum.
+    // Largest displacement of the workgroup; non-negative floats order like
+    // their bit patterns, so a 64-bit atomicMax keeps the epoch's maximum.
+    // The atomic is skipped when the stored value is already as large (all
+    // workgroups hit one address, and most would not raise it).
 #pragma unroll
     for (int s = 1; s < kWave; s <<= 1) d = fmaxf(d, __shfl_xor(d, s, kWave));
-    if ((threadIdx.x & (kWave - 1)) == 0)
-        atomicMax(&ctr->drift, ((unsigned long long)epoch << 32) | __float_as_uint(d));
+    __shared__ float s_d[256 / kWave];
+    if ((threadIdx.x & (kWave - 1)) == 0) s_d[threadIdx.x / kWave] = d;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x / kWave); ++w) d = fmaxf(d, s_d[w]);
+        const unsigned long long v = ((unsigned long long)epoch << 32) | __float_as_uint(d);
+        const unsigned long long cur =
+            __hip_atomic_load(&ctr->drift, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (v > cur) atomicMax(&ctr->drift, v);
+    }
 }
 
 void launch_refit(IndexBuffers &b, const float *x, const float *y, int64_t n, uint32_t epoch,
@@ -826,8 +951,9 @@ void launch_refit(IndexBuffers &b, const float *x, const float *y, int64_t n, ui
 {
     if (n <= 0) return;
     const int T = 256;
-    k_refit<<<(uint32_t)((n + T - 1) / T), T, 0, s>>>(x, y, (uint32_t)n, b.pts, b.anchor, b.ctr,
-                                                     epoch);
+    const int64_t g = (n + T - 1) / T;
+    k_refit<<<(uint32_t)(g < 1024 ? g : 1024), T, 0, s>>>(x, y, (uint32_t)n, b.pts, b.anchor, b.ctr,
+                                                         epoch);
 }
 
 int64_t node_capacity(int64_t n, int th, int L)
@@ -853,18 +979,15 @@ void launch_build_index(IndexBuffers &b, const float *x, const float *y, int64_t
                              words, epoch);
     const int res = launch_radix_sort(b.sort, n, 2 * kCodeLevels, s, b.xy, b.pts, b.anchor);
     const uint32_t *codes = b.sort.keys[res];
-    k_leaf_flags<<<g, T, 0, s>>>(codes, nn, th, L, b.flags);
-    // The exclusive scan goes to the other value buffer; its sum is the leaf
-    // count.
-    uint32_t *excl = b.sort.vals[res ^ 1];
-    launch_exclusive_scan(b.flags, excl, n, b.scan[0], &b.ctr->n_leaves, s);
-    k_leaf_emit<<<g, T, 0, s>>>(b.flags, excl, nn, b.leaf_of, b.leaf_begin, b.leaf_end);
-    // Leaf-bounded kernels: a fixed grid striding over the device-side count.
-    const uint32_t gl = g < 512 ? g : 512;
-    k_leaf_info<<<gl, T, 0, s>>>(codes, nn, th, L, b.leaf_begin, b.leaf_end, b.ctr, b.leaf_level,
-                                b.leaf_code, b.cnt_f, b.cnt_r, epoch);
-    launch_exclusive_scan(b.cnt_f, b.cnt_f, n, b.scan[1], &b.ctr->n_nodes, s, &b.ctr->n_leaves);
-    launch_exclusive_scan(b.cnt_r, b.cnt_r, n, b.scan[2], nullptr, s, &b.ctr->n_leaves);
+    // Binary-search steps over a window of th positions.
+    int steps = 1;
+    while ((1ll << steps) <= (int64_t)th + 1) ++steps;
+    const uint32_t ns = (uint32_t)((n + kScanTile - 1) / kScanTile);
+    k_leaves<<<ns, kScanThreads, 0, s>>>(codes, nn, th, L, steps, b.scan[0], b.ctr, b.leaf_of,
+                                         b.leaf_begin, b.leaf_end);
+    k_leaf_nodes<<<ns, kScanThreads, 0, s>>>(codes, nn, th, L, b.leaf_begin, b.leaf_end, b.scan[1],
+                                             b.scan[2], b.ctr, b.leaf_level, b.leaf_code, b.cnt_f,
+                                             b.cnt_r, epoch);
     const uint32_t gn = (uint32_t)((n + T / kLevelLanes - 1) / (T / kLevelLanes));
     k_node_emit<<<gn < 8192 ? gn : 8192, T, 0, s>>>(codes, nn, b.leaf_begin, b.leaf_end,
                                                    b.leaf_level, b.leaf_code,

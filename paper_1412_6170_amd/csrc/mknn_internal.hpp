@@ -13,7 +13,7 @@ constexpr int kWave = 64;             // CDNA wavefront width
 constexpr int kRadixBits = 8;         // LSD radix sort digit
 constexpr int kRadixBins = 1 << kRadixBits;
 constexpr int kSortThreads = 256;     // one workgroup = 4 waves
-constexpr int kSortItems = 8;         // keys per thread per tile
+constexpr int kSortItems = 16;        // keys per thread per tile
 constexpr int kSortTile = kSortThreads * kSortItems;
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;
@@ -99,7 +99,6 @@ struct IndexBuffers {
     int32_t *inv;           // sorted position of each object id (built on demand)
     int32_t *leaf_of;       // leaf index of each sorted position
     // leaves
-    uint32_t *flags;        // leaf-start flags -> exclusive scan
     int32_t *leaf_begin, *leaf_end;
     int32_t *leaf_level;
     uint32_t *leaf_code;       // code of each leaf's first object

@@ -144,6 +144,59 @@ __device__ __forceinline__ void bitonic_sort(uint64_t (&b)[N])
     }
 }
 
+// Batcher's odd-even merge sort (N a power of two): fewer compare-exchanges
+// than the bitonic network (63 instead of 80 for N = 16), all ascending.
+// The comparator list is generated at compile time.
+template <int N>
+struct OddEvenNet {
+    int lo[N * N], hi[N * N];  // generous bound on the comparator count
+    int count = 0;
+    constexpr void add(int a, int b)
+    {
+        lo[count] = a;
+        hi[count] = b;
+        ++count;
+    }
+    constexpr void merge(int base, int n, int r)
+    {
+        const int m = r * 2;
+        if (m < n) {
+            merge(base, n, m);
+            merge(base + r, n, m);
+            for (int i = base + r; i + r < base + n; i += m) add(i, i + r);
+        } else {
+            add(base, base + r);
+        }
+    }
+    constexpr void sort(int base, int n)
+    {
+        if (n > 1) {
+            const int m = n / 2;
+            sort(base, m);
+            sort(base + m, m);
+            merge(base, n, 1);
+        }
+    }
+    constexpr OddEvenNet() : lo(), hi() { sort(0, N); }
+};
+
+template <int N>
+struct OddEven {
+    static constexpr OddEvenNet<N> net{};
+};
+
+template <int N, int... I>
+__device__ __forceinline__ void oddeven_apply(uint64_t (&b)[N], std::integer_sequence<int, I...>)
+{
+    (cmp_swap(b[OddEven<N>::net.lo[I]], b[OddEven<N>::net.hi[I]]), ...);
+}
+
+template <int N>
+__device__ __forceinline__ void oddeven_sort(uint64_t (&b)[N])
+{
+    oddeven_apply<N>(b, std::make_integer_sequence<int, OddEven<N>::net.count>{});
+}
+
 template <int N, int STRIDE, int I>
 __device__ __forceinline__ void merge_ce(uint64_t (&a)[N])
 {
@@ -177,7 +230,7 @@ __device__ __forceinline__ void bitonic_merge(uint64_t (&a)[N])
 // wavefront every lane would pay for any lane's insertion); they are
 // appended to a lane-private queue of P keys in LDS.  When some lane's
 // queue is full -- and once at the end -- every lane merges its queue into
-// a[]: the queue is sorted with a bitonic network, the lower K keys of
+// a[]: the queue is sorted with a sorting network, the lower K keys of
 // a[] and the queue are taken with one min against the reversed queue
 // (which leaves a bitonic sequence) and a bitonic merge sorts them.
 //
@@ -232,7 +285,7 @@ struct Selector {
 #pragma unroll
         for (int s = 0; s < P; ++s)
             b[s] = ((uint32_t)s < cnt && (uint32_t)b[s] != excl) ? b[s] : kKeyMax;
-        bitonic_sort<P>(b);
+        oddeven_sort<P>(b);
 #pragma unroll
         for (int i = K - P; i < K; ++i) a[i] = key_min(a[i], b[K - 1 - i]);
         bitonic_merge<K>(a);
