@@ -21,8 +21,10 @@ Prints one JSON line: queries/s over the K timed ticks, p50/p99 tick latency,
 a roofline entry for the dominant kernel (the leaf-sweep query kernel,
 algorithmic bytes over its mean device time from the library's HIP events on
 the stream it runs on), the same ticks replayed as captured HIP graphs, the
-same ticks with index reuse (refit ticks between rebuilds, Sec. 4.1), and
-the CPU oracle timed on the host cores on a bounded sample.
+same ticks with two in flight on two streams (a tick's build overlapping
+the previous tick's query), the same ticks with index reuse (refit ticks
+between rebuilds, Sec. 4.1), and the CPU oracle timed on the host cores on
+a bounded sample.
 """
 import argparse
 import json
@@ -205,6 +207,8 @@ def main():
                     help="also replay the ticks as captured HIP graphs (default on)")
     ap.add_argument("--no-graph", dest="graph", action="store_false")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-pipeline", dest="pipeline", action="store_false", default=True,
+                    help="skip the line with two ticks in flight on two streams")
     ap.add_argument("--no-reuse", dest="reuse", action="store_false", default=True,
                     help="skip the index-reuse line (refit ticks under the rebuild policy)")
     ap.add_argument("--reuse-factor", type=float, default=1.3,
@@ -354,6 +358,43 @@ def main():
                         "p99_tick_ms": float(np.percentile(glat, 99))}
         del graphs
         gctx.close()
+
+    if args.pipeline:
+        # Two ticks in flight: tick s runs (build + query) on stream s % 2
+        # with its own context, so a tick's index build overlaps the previous
+        # tick's query.  Every tick still builds its index and answers all
+        # queries.
+        pstreams = [torch.cuda.Stream(), torch.cuda.Stream()]  # default priority
+        pctx = [binding.Context(n, nq, k, leaf_capacity=out["config"]["leaf_capacity"], k_hint=k,
+                                stream=ps.cuda_stream) for ps in pstreams]
+
+        def pstep(s):
+            c = pctx[s % 2]
+            x, y = dev[s % w.ticks]
+            c.load_positions(x, y)
+            c.advance_tick()
+            c.query(k=k, nq=nq)
+
+        for s in range(args.warmup):
+            pstep(s)
+        torch.cuda.synchronize()
+        pstarts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+        pends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+        t0 = time.perf_counter()
+        for s in range(args.steps):
+            pstarts[s].record(pstreams[s % 2])
+            pstep(s)
+            pends[s].record(pstreams[s % 2])
+        torch.cuda.synchronize()
+        pwall = time.perf_counter() - t0
+        plat = np.array([a.elapsed_time(b) for a, b in zip(pstarts, pends)])
+        out["pipelined"] = {"value": args.steps * nq / pwall, "unit": "queries/s",
+                            "ms_per_step": pwall * 1e3 / args.steps,
+                            "p50_tick_ms": float(np.percentile(plat, 50)),
+                            "p99_tick_ms": float(np.percentile(plat, 99)),
+                            "ticks_in_flight": 2}
+        for c in pctx:
+            c.close()
 
     if args.reuse:
         # The same ticks with index reuse (Sec. 4.1): refit ticks while the
