@@ -317,32 +317,40 @@ struct Lane {
     }
 
     // Every lane evaluates every object of the sorted range [b, e).  The
-    // range is wave-uniform, so objects arrive through scalar loads, two per
-    // step, with the next two requested before the current ones are used.
+    // range is wave-uniform; it is staged through LDS in chunks of 64
+    // records (one 16-byte load per lane, the next chunk requested before
+    // the current one is evaluated), and each record is then read by all
+    // lanes at once (an LDS broadcast), two per step.
     // Invariant between steps (and between sweeps): every queue holds at
     // most P-2 keys, so a step's two writes stay inside the queue; a merge
     // runs as soon as a queue holds more.
-    __device__ __forceinline__ void sweep(const Point *__restrict__ pts, int32_t b, int32_t e)
+    __device__ __forceinline__ void sweep(const Point *__restrict__ pts, int32_t b, int32_t e,
+                                          Point *stage)
     {
         if (b >= e) return;
         n_cand += (uint32_t)(e - b);
         ++n_leaf;
-        int32_t j = b;
-        if (e - b >= 2) {
-            Point c0 = pts[j], c1 = pts[j + 1];
-            for (; j + 2 <= e; j += 2) {
-                const int32_t jn = j + 4 <= e ? j + 2 : j;
-                const Point n0 = pts[jn], n1 = pts[jn + 1];
-                offer(c0);
-                offer(c1);
+        const int lane = threadIdx.x & (kWave - 1);
+        const uint4 *src = reinterpret_cast<const uint4 *>(pts);
+        uint4 *dst = reinterpret_cast<uint4 *>(stage);
+        uint4 next = src[b + min(lane, e - b - 1)];
+        for (int32_t c0 = b; c0 < e; c0 += kWave) {
+            const int32_t m = min(kWave, e - c0);
+            dst[lane] = next;
+            const int32_t c1 = c0 + kWave;
+            if (c1 < e) next = src[c1 + min(lane, e - c1 - 1)];
+            int32_t j = 0;
+            for (; j + 2 <= m; j += 2) {
+                const Point p0 = stage[j], p1 = stage[j + 1];
+                offer(p0);
+                offer(p1);
                 merge_if(sel.cnt > (uint32_t)(P - 2));
-                c0 = n0;
-                c1 = n1;
             }
-        }
-        if (j < e) {
-            offer(pts[j]);
-            merge_if(sel.cnt > (uint32_t)(P - 2));
+            if (j < m) {
+                const Point p0 = stage[j];
+                offer(p0);
+                merge_if(sel.cnt > (uint32_t)(P - 2));
+            }
         }
     }
 
@@ -362,7 +370,8 @@ struct Lane {
 template <int K, int P>
 __device__ __forceinline__ int32_t walk_step(Lane<K, P> &ln, const Node *__restrict__ tab,
                                              int32_t pos, int32_t total,
-                                             const Point *__restrict__ pts, int32_t n)
+                                             const Point *__restrict__ pts, int32_t n,
+                                             Point *stage)
 {
     while (pos < total) {
         const Node nd = tab[pos];
@@ -373,7 +382,7 @@ __device__ __forceinline__ int32_t walk_step(Lane<K, P> &ln, const Node *__restr
             continue;
         }
         if (nd.leaf >= 0) {
-            ln.sweep(pts, max(nd.begin, 0), min(nd.end, n));
+            ln.sweep(pts, max(nd.begin, 0), min(nd.end, n), stage);
             return next;
         }
         ++pos;
@@ -403,6 +412,8 @@ template <int K, int P>
 __global__ __launch_bounds__(kWave) void k_knn_tiles(QueryArgs qa)
 {
     __shared__ uint64_t s_queue[P * kWave];
+    __shared__ Point s_stage[kWave];
+    Point *stage = s_stage;
     const int lane = threadIdx.x;
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const uint32_t t = tile * kWave + lane;
@@ -489,7 +500,7 @@ __global__ __launch_bounds__(kWave) void k_knn_tiles(QueryArgs qa)
     l1 = __builtin_amdgcn_readfirstlane(l1);
 
     // First iteration: the own leaves.
-    ln.sweep(qa.pts, max(qa.leaf_begin[l0], 0), min(qa.leaf_end[l1], (int32_t)qa.n));
+    ln.sweep(qa.pts, max(qa.leaf_begin[l0], 0), min(qa.leaf_end[l1], (int32_t)qa.n), stage);
 
     // Subsequent iterations: alternate the two sub-visits.
     const int32_t total = min((int32_t)qa.ctr->n_nodes, qa.node_cap);
@@ -503,7 +514,8 @@ __global__ __launch_bounds__(kWave) void k_knn_tiles(QueryArgs qa)
         // so the list is not duplicated across two inlined sweeps.
         const bool fw = (right && rf < total) || rl >= total;
         const int32_t pos =
-            walk_step<K, P>(ln, fw ? qa.fwd : qa.rev, fw ? rf : rl, total, qa.pts, (int32_t)qa.n);
+            walk_step<K, P>(ln, fw ? qa.fwd : qa.rev, fw ? rf : rl, total, qa.pts, (int32_t)qa.n,
+                            stage);
         rf = fw ? pos : rf;
         rl = fw ? rl : pos;
         right = !right;
