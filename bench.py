@@ -42,7 +42,7 @@ HBM_PEAK_GBS = 8000.0
 TH_CANDIDATES = (16, 24, 32, 48, 64, 96, 128, 192)
 # Leaf capacity used when --autotune is not given: the autotuner's choice on
 # MI355X for each workload (device time per tick over TH_CANDIDATES).
-TUNED_LEAF_CAPACITY = {"clustered_1m": 64, "uniform_10k": 32, "network_4m": 64, "mixed_16m": 192}
+TUNED_LEAF_CAPACITY = {"clustered_1m": 64, "uniform_10k": 32, "network_4m": 64, "mixed_16m": 64}
 CPU_SAMPLE_SECONDS = 10.0
 
 # HBM bytes per launch of the query kernel on clustered_1m at the tuned leaf
@@ -71,17 +71,19 @@ def measured_traffic(workload, leaf_capacity):
     return m["fetch_bytes"] + m["write_bytes"]
 
 
-def query_kernel_bytes(n, nq, k):
+def query_kernel_bytes(n, nq, entries):
     """Algorithmic bytes of one launch of the query kernel: every sorted
     object read once (x, y, id: 12 B) and every result row written once
-    (k ids + k squared distances + a count: 8k + 4 B)."""
-    return 12 * n + nq * (8 * k + 4)
+    (k ids + k squared distances + a count: 8k + 4 B per query; entries is
+    the sum of k over the queries)."""
+    return 12 * n + 8 * entries + 4 * nq
 
 
-def tick_bytes(n, nq, k):
+def tick_bytes(n, nq, entries, subset):
     """Algorithmic bytes of a whole tick: positions read (8 B), sorted
-    objects written (12 B) and read back (12 B), results written."""
-    return 32 * n + nq * (8 * k + 4)
+    objects written (12 B) and read back (12 B), the query list read when
+    a subset queries (issuer and k: 8 B per query), results written."""
+    return 32 * n + (8 * nq if subset else 0) + 8 * entries + 4 * nq
 
 
 def host_threads():
@@ -93,38 +95,37 @@ def host_threads():
 
 
 def cpu_baseline(w, host_ticks):
-    """The oracle as it stands: quadtree build plus every query of a tick,
+    """The oracle as it stands: quadtree build plus the queries of a tick,
     split by query over the host threads, repeated over the workload's ticks
-    until at least CPU_SAMPLE_SECONDS have passed."""
+    until at least CPU_SAMPLE_SECONDS have passed.  Above 2M queries per
+    tick a fixed random sample of 1M of them is answered."""
     import oracle
-    k = w.k
     threads = host_threads()
-    x0, y0 = host_ticks[0]
-    oracle.knn(x0[:20000], y0[:20000], k=k, threads=threads)  # load + warm the library
-    done = 0
+    x0, y0, _, _ = host_ticks[0]
+    oracle.knn(x0[:20000], y0[:20000], k=8, threads=threads)  # load + warm the library
+    rng = np.random.default_rng(1)
+    done, queries = 0, 0
     t0 = time.perf_counter()
     while True:
-        x, y = host_ticks[done % len(host_ticks)]
-        oracle.knn(x, y, k=k, threads=threads)
+        x, y, iss, ks = host_ticks[done % len(host_ticks)]
+        nq = len(x) if iss is None else len(iss)
+        if nq > 2_000_000:
+            pick = np.sort(rng.choice(nq, 1_000_000, replace=False))
+            iss = pick.astype(np.int32) if iss is None else iss[pick]
+            ks = None if ks is None else ks[pick]
+            nq = len(pick)
+        if ks is None:
+            oracle.knn(x, y, issuers=iss, k=w.k, threads=threads)
+        else:
+            oracle.knn(x, y, issuers=iss, ks=ks, threads=threads)
         done += 1
+        queries += nq
         dt = time.perf_counter() - t0
         if dt >= CPU_SAMPLE_SECONDS:
             break
-    return {"value": done * len(x0) / dt, "unit": "queries/s", "cores": threads, "kind": "oracle",
-            "sample": "%d ticks of %s (cycling over its %d ticks): index build + all %d queries "
-                      "(k=%d) per tick, %.1f s" % (done, w.name, len(host_ticks), len(x0), k, dt)}
-
-
-def copy_calibration():
-    import torch
-    torch.cuda.set_device(0)
-    src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
-    dst = torch.empty_like(src)
-    for _ in range(5):
-        dst.copy_(src)
-    torch.cuda.synchronize()
-    print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": src.numel() * 4,
-                      "repeats": 5}), flush=True)
+    return {"value": queries / dt, "unit": "queries/s", "cores": threads, "kind": "oracle",
+            "sample": "%d ticks of %s (cycling over %d generated ticks): index build + %d "
+                      "queries in all, %.1f s" % (done, w.name, len(host_ticks), queries, dt)}
 
 
 def serving_bench(args):
@@ -198,11 +199,19 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="clustered_1m")
+    ap.add_argument("--ticks", type=int, default=0,
+                    help="generate at most this many ticks and cycle over them (0: all, "
+                         "but at most 10 for workloads above 2M objects)")
     ap.add_argument("--leaf-capacity", type=int, default=0,
                     help="leaf capacity; 0 = the tuned value for the workload %s"
                          % (TUNED_LEAF_CAPACITY,))
     ap.add_argument("--autotune", action="store_true",
                     help="choose the leaf capacity during warm-up over %s" % (TH_CANDIDATES,))
+    ap.add_argument("--th-candidates", default="",
+                    help="comma-separated leaf capacities for --autotune")
+    ap.add_argument("--group-k", action="store_true",
+                    help="variable k: answer each k class with its own list size "
+                         "(MKNN_FLAG_GROUP_K)")
     ap.add_argument("--graph", action="store_true", default=True,
                     help="also replay the ticks as captured HIP graphs (default on)")
     ap.add_argument("--no-graph", dest="graph", action="store_false")
@@ -246,31 +255,56 @@ def main():
     torch.cuda.set_device(0)
     w = workloads.WORKLOADS[args.workload]()
     n, k = w.n, w.k
-    nq = n
-    print("bench: generating %d ticks of %s" % (w.ticks, w.name), file=sys.stderr, flush=True)
-    dev, host = [], []
-    for t in range(w.ticks):
-        x, y, _, _, _ = w.tick(t)
-        host.append((x, y))
+    n_ticks = args.ticks or (w.ticks if w.n <= 2_000_000 else min(w.ticks, 10))
+    n_ticks = min(n_ticks, w.ticks)
+    print("bench: generating %d ticks of %s" % (n_ticks, w.name), file=sys.stderr, flush=True)
+    # Per generated tick: device positions, and the device query list when a
+    # subset of the objects queries (issuers and per-query k).
+    dev, host, queries = [], [], []
+    for t in range(n_ticks):
+        x, y, iss, ks, _ = w.tick(t)
+        host.append((x, y, iss, ks))
         dev.append((torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()))
+        if iss is None:
+            queries.append((None, None, n, n * k))
+        else:
+            queries.append((torch.from_numpy(iss).cuda(), torch.from_numpy(ks).cuda(), len(iss),
+                            int(np.sum(ks, dtype=np.int64))))
+        del x, y
     torch.cuda.synchronize()
+    subset = queries[0][0] is not None
+    nq_max = max(q[2] for q in queries)
+    nq_mean = float(np.mean([q[2] for q in queries]))
+    entries_mean = float(np.mean([q[3] for q in queries]))
+
+    def tick_nq(s):
+        return queries[s % n_ticks][2]
+
+    def run_query(c, s):
+        iss, ks, nq_s, _ = queries[s % n_ticks]
+        if iss is None:
+            c.query(k=k, nq=nq_s)
+        else:
+            c.query(issuers=iss, ks=ks)
 
     stream = torch.cuda.Stream()
-    th0 = (min(TH_CANDIDATES) if args.autotune else
+    cands = (tuple(int(v) for v in args.th_candidates.split(",")) if args.th_candidates
+             else TH_CANDIDATES)
+    th0 = (min(cands) if args.autotune else
            args.leaf_capacity or TUNED_LEAF_CAPACITY.get(w.name, 0))
-    ctx = binding.Context(n, nq, k, leaf_capacity=th0, k_hint=k, stream=stream.cuda_stream,
-                          timing=True, counters=args.counters)
+    ctx = binding.Context(n, nq_max, k, leaf_capacity=th0, k_hint=k, stream=stream.cuda_stream,
+                          timing=True, counters=args.counters, group_k=args.group_k)
 
     def step(s):
-        x, y = dev[s % w.ticks]
+        x, y = dev[s % n_ticks]
         ctx.load_positions(x, y)
         ctx.advance_tick()
-        ctx.query(k=k, nq=nq)
+        run_query(ctx, s)
 
     with torch.cuda.stream(stream):
         tune = None
         if args.autotune:
-            best, times = binding.autotune_leaf_capacity(ctx, step, TH_CANDIDATES)
+            best, times = binding.autotune_leaf_capacity(ctx, step, cands)
             tune = {"chosen": best, "device_ms_per_tick": {str(t): v for t, v in times.items()}}
             print("bench: autotuned leaf capacity %d (%s)" % (best, tune), file=sys.stderr,
                   flush=True)
@@ -283,9 +317,10 @@ def main():
         ctx.sync()
         st = ctx.stats()
 
-    value = args.steps * nq / wall
+    total_q = sum(tick_nq(s) for s in range(args.steps))
+    value = total_q / wall
     kern_ms = st["ms_query_main_mean"]
-    kern_bytes = query_kernel_bytes(n, nq, k)
+    kern_bytes = query_kernel_bytes(n, nq_mean, entries_mean)
     achieved = kern_bytes / (kern_ms * 1e-3) / 1e9
     tick_ms = float(np.mean(lat))
     out = {
@@ -301,18 +336,22 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": w.name, "objects": n, "queries_per_tick": nq, "k": k,
-                   "ticks": w.ticks, "leaf_capacity": st["leaf_capacity"],
-                   "description": w.description},
+        "config": {"workload": w.name, "objects": n, "queries_per_tick": nq_mean,
+                   "k": k if not subset else "per query, mean %.1f" % (entries_mean / nq_mean),
+                   "ticks": w.ticks, "ticks_generated": n_ticks,
+                   "leaf_capacity": st["leaf_capacity"], "description": w.description},
         "p50_tick_ms": float(np.percentile(lat, 50)),
         "p99_tick_ms": float(np.percentile(lat, 99)),
         "device_ms_build_mean": st["ms_build_mean"],
         "device_ms_query_mean": st["ms_query_mean"],
-        "tick_hbm_frac": tick_bytes(n, nq, k) / (tick_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "tick_hbm_frac": tick_bytes(n, nq_mean, entries_mean, subset) / (tick_ms * 1e-3) / 1e9
+        / HBM_PEAK_GBS,
         "leaves": st["leaves"],
         "deepest_level": st["deepest_level"],
         "autotune": tune,
-        "roofline": {"bound": "hbm", "kernel": "k_knn_tiles<32,16> (leaf sweeps)",
+        "roofline": {"bound": "hbm", "kernel": "k_knn_tiles (leaf sweeps), k class %d" % (
+                         8 if k <= 8 else 16 if k <= 16 else 32 if k <= 32 else 64 if k <= 64
+                         else 128),
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(w.name, st["leaf_capacity"]),
@@ -331,28 +370,28 @@ def main():
     if args.graph:
         # The same ticks, each captured once as a HIP graph (one graph per
         # tick's input buffers) and replayed; no timing events inside.
-        gctx = binding.Context(n, nq, k, leaf_capacity=out["config"]["leaf_capacity"], k_hint=k,
-                               stream=stream.cuda_stream)
+        gctx = binding.Context(n, nq_max, k, leaf_capacity=out["config"]["leaf_capacity"],
+                               k_hint=k, stream=stream.cuda_stream, group_k=args.group_k)
 
         def gstep(s):
-            x, y = dev[s % w.ticks]
+            x, y = dev[s % n_ticks]
             gctx.load_positions(x, y)
             gctx.advance_tick()
-            gctx.query(k=k, nq=nq)
+            run_query(gctx, s)
 
         with torch.cuda.stream(stream):
             gstep(0)
             gctx.sync()
             graphs = []
-            for t in range(w.ticks):
+            for t in range(n_ticks):
                 g = torch.cuda.CUDAGraph()
                 with torch.cuda.graph(g, stream=stream):
                     gstep(t)
                 graphs.append(g)
             for s in range(args.warmup):
-                graphs[s % w.ticks].replay()
-            gwall, glat = timed(stream, args.steps, lambda s: graphs[s % w.ticks].replay())
-        out["graph"] = {"value": args.steps * nq / gwall, "unit": "queries/s",
+                graphs[s % n_ticks].replay()
+            gwall, glat = timed(stream, args.steps, lambda s: graphs[s % n_ticks].replay())
+        out["graph"] = {"value": total_q / gwall, "unit": "queries/s",
                         "ms_per_step": gwall * 1e3 / args.steps,
                         "p50_tick_ms": float(np.percentile(glat, 50)),
                         "p99_tick_ms": float(np.percentile(glat, 99))}
@@ -365,15 +404,17 @@ def main():
         # tick's query.  Every tick still builds its index and answers all
         # queries.
         pstreams = [torch.cuda.Stream(), torch.cuda.Stream()]  # default priority
-        pctx = [binding.Context(n, nq, k, leaf_capacity=out["config"]["leaf_capacity"], k_hint=k,
-                                stream=ps.cuda_stream) for ps in pstreams]
+        pctx = [binding.Context(n, nq_max, k, leaf_capacity=out["config"]["leaf_capacity"],
+                                k_hint=k, stream=ps.cuda_stream, group_k=args.group_k)
+                for ps in pstreams]
 
         def pstep(s):
             c = pctx[s % 2]
-            x, y = dev[s % w.ticks]
+            x, y = dev[s % n_ticks]
             c.load_positions(x, y)
             c.advance_tick()
-            c.query(k=k, nq=nq)
+            with torch.cuda.stream(pstreams[s % 2]):
+                run_query(c, s)
 
         for s in range(args.warmup):
             pstep(s)
@@ -388,7 +429,7 @@ def main():
         torch.cuda.synchronize()
         pwall = time.perf_counter() - t0
         plat = np.array([a.elapsed_time(b) for a, b in zip(pstarts, pends)])
-        out["pipelined"] = {"value": args.steps * nq / pwall, "unit": "queries/s",
+        out["pipelined"] = {"value": total_q / pwall, "unit": "queries/s",
                             "ms_per_step": pwall * 1e3 / args.steps,
                             "p50_tick_ms": float(np.percentile(plat, 50)),
                             "p99_tick_ms": float(np.percentile(plat, 99)),
@@ -401,21 +442,22 @@ def main():
         # last query stays within reuse_factor of the time after the last
         # full build, else rebuild.  The policy reads the previous query's
         # device time each tick (a host wait inside the timed region).
-        rctx = binding.Context(n, nq, k, leaf_capacity=out["config"]["leaf_capacity"], k_hint=k,
-                               stream=stream.cuda_stream, timing=True)
+        rctx = binding.Context(n, nq_max, k, leaf_capacity=out["config"]["leaf_capacity"],
+                               k_hint=k, stream=stream.cuda_stream, timing=True,
+                               group_k=args.group_k)
         pol = binding.ReusePolicy(factor=args.reuse_factor)
 
         def rstep(s):
-            x, y = dev[s % w.ticks]
+            x, y = dev[s % n_ticks]
             pol.tick(rctx, x, y)
-            rctx.query(k=k, nq=nq)
+            run_query(rctx, s)
 
         with torch.cuda.stream(stream):
             for s in range(args.warmup):
                 rstep(s)
             pol.rebuilds = pol.refits = 0
             rwall, rlat = timed(stream, args.steps, rstep)
-        out["reuse"] = {"value": args.steps * nq / rwall, "unit": "queries/s",
+        out["reuse"] = {"value": total_q / rwall, "unit": "queries/s",
                         "ms_per_step": rwall * 1e3 / args.steps,
                         "p50_tick_ms": float(np.percentile(rlat, 50)),
                         "p99_tick_ms": float(np.percentile(rlat, 99)),

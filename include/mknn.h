@@ -76,6 +76,13 @@ extern "C" {
 /* mknn_config.flags */
 #define MKNN_FLAG_TIMING 1   /* record per-phase device times (mknn_stats) */
 #define MKNN_FLAG_COUNTERS 2 /* count the query kernel's work (mknn_stats) */
+/* Variable-k queries: group the queries by the size class of their k
+ * (lists of 8, 16, 32, 64, 128 keys) and answer each class with its own
+ * list size, instead of one pass sized for the largest k.  Pays off when
+ * queries with similar k are spatially close (each class stays dense);
+ * when k is drawn independently per query, each class is sparse in space
+ * and one pass is faster.  Results are the same either way. */
+#define MKNN_FLAG_GROUP_K 4
 
 typedef struct mknn_ctx mknn_ctx;
 

@@ -18,6 +18,7 @@ MKNN_HOST = 0
 MKNN_DEVICE = 1
 MKNN_FLAG_TIMING = 1
 MKNN_FLAG_COUNTERS = 2
+MKNN_FLAG_GROUP_K = 4
 MKNN_K_LIMIT = 128
 STATUS = {0: "MKNN_OK", -1: "MKNN_E_INVAL", -2: "MKNN_E_RANGE", -3: "MKNN_E_STATE",
           -4: "MKNN_E_CAPACITY", -5: "MKNN_E_NOMEM", -6: "MKNN_E_DEVICE"}
@@ -114,7 +115,7 @@ def default_leaf_capacity(k):
 
 
 def make_config(n_max, q_max=None, k_max=32, leaf_capacity=0, max_level=0, k_hint=0, device=0,
-                stream=None, timing=False, counters=False):
+                stream=None, timing=False, counters=False, group_k=False):
     cfg = Config()
     cfg.device = device
     cfg.leaf_capacity = int(leaf_capacity)
@@ -124,7 +125,8 @@ def make_config(n_max, q_max=None, k_max=32, leaf_capacity=0, max_level=0, k_hin
     cfg.q_max = int(q_max if q_max is not None else n_max)
     cfg.stream = stream
     cfg.k_hint = int(k_hint)
-    cfg.flags = (MKNN_FLAG_TIMING if timing else 0) | (MKNN_FLAG_COUNTERS if counters else 0)
+    cfg.flags = ((MKNN_FLAG_TIMING if timing else 0) | (MKNN_FLAG_COUNTERS if counters else 0)
+                 | (MKNN_FLAG_GROUP_K if group_k else 0))
     return cfg
 
 
@@ -150,9 +152,9 @@ class Context:
     of up to k_max neighbours each."""
 
     def __init__(self, n_max, q_max=None, k_max=32, leaf_capacity=0, max_level=0, k_hint=0,
-                 device=0, stream=None, timing=False, counters=False):
+                 device=0, stream=None, timing=False, counters=False, group_k=False):
         cfg = make_config(n_max, q_max, k_max, leaf_capacity, max_level, k_hint, device, stream,
-                          timing, counters)
+                          timing, counters, group_k)
         self.cfg = cfg
         h = _vp()
         rc = lib().mknn_create(ctypes.byref(cfg), ctypes.byref(h))

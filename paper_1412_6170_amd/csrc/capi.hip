@@ -43,6 +43,7 @@ struct mknn_ctx {
     int32_t *issuers = nullptr, *ks = nullptr;  // staging of host query arrays
     float *qcx = nullptr, *qcy = nullptr;       // staging of host free centres
     QPoint *qpts = nullptr;                     // free centres in processing order
+    uint32_t *class_bounds = nullptr;           // per-k-class query ranges [8]
     uint32_t *kcount = nullptr, *kscan = nullptr, *ktotal = nullptr;
     int64_t *offsets = nullptr;
     int32_t *out_ids = nullptr;
@@ -107,6 +108,20 @@ int check_launch(mknn_ctx *c, const char *what)
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(c, e, what);
     return MKNN_OK;
+}
+
+// Selection-list class of a k: lists of 8 << class keys.
+int class_slot(int k)
+{
+    return k <= 8 ? 0 : k <= 16 ? 1 : k <= 32 ? 2 : k <= 64 ? 3 : 4;
+}
+
+// Bits that hold a sorted position below n.
+int pos_bits(int64_t n)
+{
+    int b = 1;
+    while (b < 31 && ((int64_t)1 << b) < n) ++b;
+    return b;
 }
 
 int bits_for(int64_t n)
@@ -198,6 +213,7 @@ void for_each_buffer(mknn_ctx *c, F &&f)
     f(c->qcx, Q);
     f(c->qcy, Q);
     f(c->qpts, Q);
+    f(c->class_bounds, 8);
     f(c->kcount, Q);
     f(c->kscan, Q);
     f(c->ktotal, 1);
@@ -475,6 +491,9 @@ QueryArgs base_query_args(mknn_ctx *c, int64_t nq, const int32_t *ks, int32_t k_
     qa.out_cnt = c->out_cnt;
     qa.counters = (c->cfg.flags & MKNN_FLAG_COUNTERS) ? c->counters : nullptr;
     qa.build_epoch = c->build_epoch;
+    qa.pos_mask = 0xffffffffu;
+    qa.class_bounds = nullptr;
+    qa.klass = 0;
     return qa;
 }
 
@@ -629,8 +648,11 @@ int mknn_query(mknn_ctx *c, const int32_t *issuers, const int32_t *ks, int64_t n
     if (!ks && (k_uniform < 1 || k_uniform > c->k_max))
         return fail(c, MKNN_E_INVAL, "k outside [1, k_max]%s");
     int kmax_call = ks ? c->k_max : k_uniform;
+    // k classes that occur (bit c: lists of 8 << c keys); unknown for device ks.
+    unsigned present = 0x1fu;
     if (where == MKNN_HOST) {
         int kmx = 1;
+        unsigned seen = 0;
         for (int64_t i = 0; i < nq; ++i) {
             if (issuers && (issuers[i] < 0 || issuers[i] >= c->n))
                 return fail(c, MKNN_E_INVAL, "issuer %s outside [0,n)",
@@ -640,9 +662,13 @@ int mknn_query(mknn_ctx *c, const int32_t *issuers, const int32_t *ks, int64_t n
                     return fail(c, MKNN_E_INVAL, "k of query %s outside [1,k_max]",
                                 std::to_string(i).c_str());
                 if (ks[i] > kmx) kmx = ks[i];
+                seen |= 1u << class_slot(ks[i]);
             }
         }
-        if (ks) kmax_call = kmx;
+        if (ks) {
+            kmax_call = kmx;
+            present = seen;
+        }
     }
     HIP_OR_FAIL(c, hipSetDevice(c->cfg.device));
     int rc = mark(c, 2);
@@ -665,7 +691,13 @@ int mknn_query(mknn_ctx *c, const int32_t *issuers, const int32_t *ks, int64_t n
 
     QueryArgs qa = base_query_args(c, nq, ks, k_uniform);
 
-    if (d_iss && nq > 0 && !c->inv_ready) {
+    // Variable k with MKNN_FLAG_GROUP_K: queries are grouped by k class
+    // (sorted by class, then by position) and each class runs with its own
+    // list size, as long as class and position fit one 32-bit sort key.
+    const int pbits = pos_bits(c->n);
+    const bool grouped =
+        (c->cfg.flags & MKNN_FLAG_GROUP_K) && d_ks && nq > 0 && pbits + 3 <= 32;
+    if ((d_iss || grouped) && nq > 0 && !c->inv_ready) {
         launch_inverse(c->ix, c->n, c->stream);
         c->inv_ready = true;
     }
@@ -679,6 +711,7 @@ int mknn_query(mknn_ctx *c, const int32_t *issuers, const int32_t *ks, int64_t n
         p.n = (uint32_t)c->n;
         p.k_max = c->k_max;
         p.inv = c->ix.inv;
+        p.class_shift = grouped ? pbits : -1;
         p.sort = c->qs;
         p.kcount = c->kcount;
         p.ctr = c->ix.ctr;
@@ -686,10 +719,17 @@ int mknn_query(mknn_ctx *c, const int32_t *issuers, const int32_t *ks, int64_t n
         p.ws_words = words;
         p.epoch = c->query_epoch;
         launch_query_prep(p, c->stream);
-        if (d_iss) {
-            const int res = launch_radix_sort(c->qs, nq, bits_for(c->n), c->stream);
+        if (d_iss || grouped) {
+            const int res =
+                launch_radix_sort(c->qs, nq, grouped ? pbits + 3 : bits_for(c->n), c->stream);
             qa.qpos = (const int32_t *)c->qs.keys[res];
             qa.qrow = (const int32_t *)c->qs.vals[res];
+            if (grouped) {
+                qa.pos_mask = (1u << pbits) - 1u;
+                launch_class_bounds(c->qs.keys[res], (uint32_t)nq, pbits, c->class_bounds,
+                                    c->stream);
+                qa.class_bounds = c->class_bounds;
+            }
         }
         if (d_ks) {
             launch_offsets(c->kcount, (uint32_t)nq, c->kscan, c->qscan, c->ktotal, c->offsets,
@@ -706,7 +746,16 @@ int mknn_query(mknn_ctx *c, const int32_t *issuers, const int32_t *ks, int64_t n
     }
     rc = mark(c, 4);
     if (rc) return rc;
-    launch_knn(qa, k_class(kmax_call), c->stream);
+    if (qa.class_bounds) {
+        const int top = class_slot(kmax_call);
+        for (int cls = 0; cls <= top; ++cls) {
+            if (!(present & (1u << cls))) continue;
+            qa.klass = cls;
+            launch_knn(qa, 8 << cls, c->stream);
+        }
+    } else {
+        launch_knn(qa, k_class(kmax_call), c->stream);
+    }
     rc = check_launch(c, "k-NN query");
     if (!rc) rc = mark(c, 5);
     if (!rc) rc = mark(c, 3);

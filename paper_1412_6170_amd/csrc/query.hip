@@ -396,16 +396,19 @@ __device__ __forceinline__ int32_t walk_step(Lane<K, P> &ln, const Node *__restr
 // regions).
 //
 // Tile order is XCD-aware: workgroups are dealt round-robin to the 8 XCDs
-// (workgroup b runs on XCD b mod 8), so workgroup b takes tile
-// (b mod 8) * (groups / 8) + b / 8.  Each XCD then works through one
+// (workgroup b runs on XCD b mod 8), so for T tiles workgroup b takes tile
+// (b mod 8) * ceil(T / 8) + b / 8.  Each XCD then works through one
 // contiguous eighth of the Morton-ordered queries, whose candidates are
-// spatially close and stay in that XCD's L2.  The grid is a multiple of 8;
-// tiles past the last query exit at once.
+// spatially close and stay in that XCD's L2.  T is the launch's own query
+// count (known on the device for a k class), so the grid may be larger;
+// workgroups past the tiles exit at once.
 constexpr uint32_t kXcds = 8;
 
-__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t groups)
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t tiles)
 {
-    return (b % kXcds) * (groups / kXcds) + b / kXcds;
+    const uint32_t per = (tiles + kXcds - 1) / kXcds;
+    const uint32_t slot = b / kXcds;
+    return slot < per ? (b % kXcds) * per + slot : 0xffffffffu;
 }
 
 template <int K, int P>
@@ -415,12 +418,18 @@ __global__ __launch_bounds__(kWave) void k_knn_tiles(QueryArgs qa)
     __shared__ Point s_stage[kWave];
     Point *stage = s_stage;
     const int lane = threadIdx.x;
-    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    // The queries of this launch: all of them, or one k class of them.
+    uint32_t q_begin = 0, q_count = qa.nq;
+    if (qa.class_bounds) {
+        q_begin = qa.class_bounds[qa.klass];
+        q_count = qa.class_bounds[qa.klass + 1] - q_begin;
+    }
+    const uint32_t tile = xcd_tile(blockIdx.x, (q_count + kWave - 1) / kWave);
+    if (tile == 0xffffffffu || tile * kWave >= q_count) return;  // whole wavefront idle
     const uint32_t t = tile * kWave + lane;
-    if (tile * kWave >= qa.nq) return;  // whole wavefront idle
 
     Lane<K, P> ln;
-    ln.active = t < qa.nq;
+    ln.active = t < q_count;
     // After refit ticks the objects have moved by up to D per axis since the
     // quadrant boxes were made; grow the boxes by D plus a margin that covers
     // the rounding of D and of the grown edges (2^-23 > 2 * 2^-25, the
@@ -431,7 +440,7 @@ __global__ __launch_bounds__(kWave) void k_knn_tiles(QueryArgs qa)
         const float d = __uint_as_float((uint32_t)dw);
         if ((uint32_t)(dw >> 32) == qa.build_epoch && d > 0.0f) ln.pad = d + 0x1p-23f;
     }
-    const uint32_t tq = ln.active ? t : qa.nq - 1;
+    const uint32_t tq = q_begin + (ln.active ? t : q_count - 1);
     // Query centre, excluded object and sorted position to start from: an
     // object's own position and id, or a free centre's insertion position.
     int32_t qp, row;
@@ -444,7 +453,7 @@ __global__ __launch_bounds__(kWave) void k_knn_tiles(QueryArgs qa)
         qp = min(max(c.pos, 0), (int32_t)qa.n - 1);
         row = qa.qrow[tq];
     } else {
-        qp = qa.qpos ? qa.qpos[tq] : (int32_t)tq;
+        qp = qa.qpos ? (int32_t)((uint32_t)qa.qpos[tq] & qa.pos_mask) : (int32_t)tq;
         const Point q = qa.pts[qp];
         ln.qx = q.x;
         ln.qy = q.y;
@@ -697,29 +706,67 @@ void launch_knn(const QueryArgs &qa, int kclass, hipStream_t s)
 // neighbours.  Device-supplied issuers and ks are range-checked here.
 // ---------------------------------------------------------------------------
 
+// Index of the selection-list size class of a k (classes of 8, 16, 32, 64
+// and 128 keys).
+__device__ __forceinline__ uint32_t class_index(int k)
+{
+    return k <= 8 ? 0u : k <= 16 ? 1u : k <= 32 ? 2u : k <= 64 ? 3u : 4u;
+}
+
+// Sort keys of the queries: the sorted position of the issuer, and with
+// class_shift >= 0 the query's k class above it, so that the sorted
+// queries are grouped by class and Morton-ordered within each class (each
+// class then runs with its own list size).  Without issuers, query q is
+// issued by object q.
 __global__ void k_query_keys(const int32_t *__restrict__ issuers, const int32_t *__restrict__ ks,
                              uint32_t nq, uint32_t n, int k_max, const int32_t *__restrict__ inv,
-                             uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
-                             uint32_t *__restrict__ kcount, IndexCounters *__restrict__ ctr,
-                             uint64_t *__restrict__ ws, int64_t ws_words, uint32_t epoch)
+                             int class_shift, uint32_t *__restrict__ keys,
+                             uint32_t *__restrict__ vals, uint32_t *__restrict__ kcount,
+                             IndexCounters *__restrict__ ctr, uint64_t *__restrict__ ws,
+                             int64_t ws_words, uint32_t epoch)
 {
     const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
     // The query sort and scan workspace starts at zero.
     for (int64_t w = q; w < ws_words; w += (int64_t)gridDim.x * blockDim.x) ws[w] = 0ull;
     if (q >= nq) return;
-    if (issuers) {
-        int32_t s = issuers[q];
-        bool ok = s >= 0 && (uint32_t)s < n;
-        if (!ok) atomicMax(&ctr->bad_issuer, epoch);
-        keys[q] = ok ? (uint32_t)inv[s] : 0u;
-        vals[q] = q;
-    }
+    uint32_t cls = 0;
     if (ks) {
         int32_t k = ks[q];
         bool ok = k >= 1 && k <= k_max;
         if (!ok) atomicMax(&ctr->bad_k, epoch);
         kcount[q] = ok ? (uint32_t)k : 1u;
+        cls = class_index(ok ? k : 1);
     }
+    if (issuers || class_shift >= 0) {
+        int32_t s = issuers ? issuers[q] : (int32_t)q;
+        bool ok = s >= 0 && (uint32_t)s < n;
+        if (!ok) atomicMax(&ctr->bad_issuer, epoch);
+        const uint32_t pos = ok ? (uint32_t)inv[s] : 0u;
+        keys[q] = class_shift >= 0 ? (pos | (cls << class_shift)) : pos;
+        vals[q] = q;
+    }
+}
+
+// First sorted query of each class (bounds[c] .. bounds[c+1] is class c).
+__global__ void k_class_bounds(const uint32_t *__restrict__ keys, uint32_t nq, int class_shift,
+                               uint32_t *__restrict__ bounds)
+{
+    const uint32_t c = threadIdx.x;
+    if (c > kQueryClasses) return;
+    const uint32_t target = c << class_shift;
+    uint32_t lo = 0, hi = nq;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (keys[mid] < target) lo = mid + 1;
+        else hi = mid;
+    }
+    bounds[c] = lo;
+}
+
+void launch_class_bounds(const uint32_t *keys, uint32_t nq, int class_shift, uint32_t *bounds,
+                         hipStream_t s)
+{
+    k_class_bounds<<<1, kWave, 0, s>>>(keys, nq, class_shift, bounds);
 }
 
 __global__ void k_widen_offsets(const uint32_t *__restrict__ excl, const uint32_t *__restrict__ total,
@@ -735,8 +782,9 @@ void launch_query_prep(const QueryPrep &p, hipStream_t s)
     const int T = 256;
     const uint32_t g = (p.nq + T - 1) / T;
     if (p.nq == 0) return;
-    k_query_keys<<<g, T, 0, s>>>(p.issuers, p.ks, p.nq, p.n, p.k_max, p.inv, p.sort.keys[0],
-                                 p.sort.vals[0], p.kcount, p.ctr, p.ws, p.ws_words, p.epoch);
+    k_query_keys<<<g, T, 0, s>>>(p.issuers, p.ks, p.nq, p.n, p.k_max, p.inv, p.class_shift,
+                                 p.sort.keys[0], p.sort.vals[0], p.kcount, p.ctr, p.ws,
+                                 p.ws_words, p.epoch);
 }
 
 void launch_offsets(const uint32_t *kcount, uint32_t nq, uint32_t *scan_out, const ScanSpace &sp,

@@ -30,6 +30,10 @@ struct QueryArgs {
                                  // order; null = object id (every object queries)
     const QPoint *qpts;          // free centres in processing order (then qpos
                                  // is unused); null = queries issued by objects
+    uint32_t pos_mask;           // bits of a qpos entry holding the position
+    const uint32_t *class_bounds;  // null, or first processing-order query of
+                                   // each k class ([kQueryClasses + 1])
+    int klass;                   // the class this launch answers
     uint32_t nq;
     const int32_t *ks;           // k per result row (range-checked); null = k_uniform
     int32_t k_uniform;
@@ -42,12 +46,15 @@ struct QueryArgs {
                                    // node visits, leaf sweeps, wavefronts]
 };
 
+constexpr int kQueryClasses = 5;  // selection lists of 8, 16, 32, 64, 128 keys
+
 struct QueryPrep {
     const int32_t *issuers;      // device, nq entries, or null
     const int32_t *ks;           // device, nq entries, or null
     uint32_t nq, n;
     int k_max;
     const int32_t *inv;
+    int class_shift;             // >= 0: put the k class above bit class_shift
     SortBuffers sort;            // keys[0]/vals[0] receive (sorted position, query)
     uint32_t *kcount;            // range-checked k per query
     IndexCounters *ctr;
@@ -79,6 +86,8 @@ void launch_point_place(const uint32_t *codes, const uint32_t *rows, uint32_t nq
                         QPoint *qpts, hipStream_t s);
 void launch_knn(const QueryArgs &qa, int kclass, hipStream_t s);
 void launch_query_prep(const QueryPrep &p, hipStream_t s);
+void launch_class_bounds(const uint32_t *keys, uint32_t nq, int class_shift, uint32_t *bounds,
+                         hipStream_t s);
 void launch_offsets(const uint32_t *kcount, uint32_t nq, uint32_t *scan_out, const ScanSpace &sp,
                     uint32_t *total, int64_t *offsets, hipStream_t s);
 

@@ -50,12 +50,14 @@ def assert_rows_equal(got, exp, what=""):
         assert same(go, eo)
 
 
-def gpu_knn(x, y, k=None, issuers=None, ks=None, th=0, L=0, k_max=None, device_inputs=False):
+def gpu_knn(x, y, k=None, issuers=None, ks=None, th=0, L=0, k_max=None, device_inputs=False,
+            group_k=False):
     n = len(x)
     nq = n if issuers is None else len(issuers)
     if k_max is None:
         k_max = int(k) if ks is None else int(np.max(ks))
-    with binding.Context(max(n, 1), max(nq, 1), k_max, leaf_capacity=th, max_level=L) as c:
+    with binding.Context(max(n, 1), max(nq, 1), k_max, leaf_capacity=th, max_level=L,
+                         group_k=group_k) as c:
         if device_inputs:
             c.load_positions(torch.from_numpy(f32(x)).cuda(), torch.from_numpy(f32(y)).cuda())
         else:
@@ -201,6 +203,30 @@ def test_subset_and_variable_k(device_inputs):
     got = gpu_knn(x, y, ks=np.full(6000, 7, np.int32), device_inputs=device_inputs)
     exp = oracle.brute_knn(x, y, ks=np.full(6000, 7, np.int32), threads=16)
     assert_rows_equal(got, exp, "all objects, ks array")
+
+
+@pytest.mark.parametrize("group_k", [False, True])
+@pytest.mark.parametrize("device_inputs", [False, True])
+def test_variable_k_every_class(device_inputs, group_k):
+    """Variable k spanning all five selection-list classes (k up to 128), in
+    one pass sized for the largest k or (MKNN_FLAG_GROUP_K) grouped by
+    class with each class at its own list size; rows come back in query
+    order either way."""
+    x, y = family("duplicates", 9000, 41)
+    rng = np.random.default_rng(8)
+    for issuers in (None, rng.choice(9000, 4000, replace=False).astype(np.int32)):
+        nq = 9000 if issuers is None else len(issuers)
+        ks = rng.integers(1, 129, nq).astype(np.int32)
+        ks[rng.random(nq) < 0.3] = 8          # a crowded class
+        say("variable k, all classes, subset=%s device=%s" % (issuers is not None, device_inputs))
+        got = gpu_knn(x, y, issuers=issuers, ks=ks, th=24, device_inputs=device_inputs,
+                      group_k=group_k)
+        exp = oracle.knn(x, y, issuers=issuers, ks=ks, th=24, threads=16)
+        assert_rows_equal(got, exp, "variable k, every class")
+    # Only two classes present (host ks launch only those).
+    ks = np.where(rng.random(9000) < 0.5, 3, 40).astype(np.int32)
+    got = gpu_knn(x, y, ks=ks, th=24, device_inputs=device_inputs, group_k=group_k)
+    assert_rows_equal(got, oracle.knn(x, y, ks=ks, th=24, threads=16), "two classes")
 
 
 def test_repeated_issuers_and_empty_query():
