@@ -3,7 +3,7 @@
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload clustered_1m]
                     [--leaf-capacity TH | --autotune] [--no-graph] [--counters]
                     [--no-cpu-baseline]
-    python bench.py --serving [--scenes 64] [--rate 1500] [--slots 4]
+    python bench.py --serving [--scenes 64] [--rate R] [--slots 4]
 
 A step is one tick of the whole hot path on device-resident inputs: the
 index build (Morton codes, radix sort, leaf split, node tables) over the
@@ -153,10 +153,15 @@ def serving_bench(args):
     ids = [s.sid for s in scenes]
     # warm-up: one tick of every scene (contexts created, kernels loaded)
     srv.run([(0.0, sid, 0) for sid in ids])
-    arrivals = serving.poisson_arrivals(ids, args.scene_ticks, rate=args.rate,
+    # Saturation: every request of the schedule present at once.
+    sat_done = srv.run([(0.0, sid, t) for sid in ids for t in range(args.scene_ticks)])
+    sat = serving.summarize(sat_done, {s.sid: s for s in scenes})
+    sat_rate = sat["requests"] / sat["makespan_s"]
+    rate = args.rate if args.rate > 0 else 0.7 * sat_rate
+    arrivals = serving.poisson_arrivals(ids, args.scene_ticks, rate=rate,
                                         seed=args.serving_seed + 1)
-    print("bench: serving %d requests at %.0f/s" % (len(arrivals), args.rate), file=sys.stderr,
-          flush=True)
+    print("bench: saturation %.0f requests/s; serving %d requests at %.0f/s" % (
+        sat_rate, len(arrivals), rate), file=sys.stderr, flush=True)
     done = srv.run(arrivals)
     summ = serving.summarize(done, {s.sid: s for s in scenes})
     out = {"metric": "served k-NN queries/s and tick latency, many scenes, continuous batching",
@@ -164,10 +169,13 @@ def serving_bench(args):
            "higher_is_better": True, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "serving_mix", "scenes": args.scenes,
                       "objects_total": int(sum(s.n for s in scenes)),
-                      "ticks_per_scene": args.scene_ticks, "rate_per_s": args.rate,
+                      "ticks_per_scene": args.scene_ticks, "rate_per_s": rate,
+                      "saturation_requests_per_s": sat_rate,
+                      "saturation_queries_per_s": sat["queries_per_s"],
                       "slots": args.slots, "hbm_budget_gib": args.hbm_budget_gib,
                       "description": "scene sizes log-uniform in [1e4, 2e6], k in {8, 32}, "
-                                     "clustered moving objects, Poisson tick requests"},
+                                     "clustered moving objects, Poisson tick requests at 0.7 x "
+                                     "the saturation rate unless --rate is given"},
            "p50_latency_ms": summ["p50_latency_ms"], "p99_latency_ms": summ["p99_latency_ms"],
            "requests": summ["requests"], "makespan_s": summ["makespan_s"],
            "admissions": srv.admissions, "evictions": srv.evictions}
@@ -231,7 +239,8 @@ def main():
                     help="serving mode: many scenes, Poisson tick requests, p50/p99 latency")
     ap.add_argument("--scenes", type=int, default=64)
     ap.add_argument("--scene-ticks", type=int, default=8)
-    ap.add_argument("--rate", type=float, default=1500.0, help="tick requests per second")
+    ap.add_argument("--rate", type=float, default=0.0,
+                    help="tick requests per second (0: 0.7 x the measured saturation rate)")
     ap.add_argument("--slots", type=int, default=4, help="ticks in flight at most")
     ap.add_argument("--hbm-budget-gib", type=float, default=64.0)
     ap.add_argument("--serving-seed", type=int, default=7)
