@@ -20,10 +20,12 @@ constexpr int kScanItems = 8;
 constexpr int kScanTile = kScanThreads * kScanItems;
 
 // One object in sorted (Morton) order.  Array of 16-byte records so one
-// scalar load fetches a whole candidate during leaf sweeps.
+// load fetches a whole candidate during leaf sweeps; the id comes first so
+// that, read into consecutive registers, it can sit next to the squared
+// distance computed from x and y as the (d2, id) selection key.
 struct __align__(16) Point {
-    float x, y;
     uint32_t id;    // object id = its index in the caller's arrays
+    float x, y;
     uint32_t code;  // level-16 Morton code, x cell in the even bits
 };
 
