@@ -80,3 +80,17 @@ def test_footprint_is_host_only_and_monotone():
     assert big > 1_000_000 * 32 * 8
     with pytest.raises(binding.MknnError):
         binding.footprint(n_max=0)
+
+
+def test_footprint_at_the_largest_sizes():
+    """n_max up to 2^31 - 1 and k_max = 128: sizes are 64-bit and grow
+    linearly (no overflow); one past the limit is rejected."""
+    top = 2 ** 31 - 1
+    a = binding.footprint(n_max=top // 2, q_max=top // 2, k_max=128, leaf_capacity=64)
+    b = binding.footprint(n_max=top, q_max=top, k_max=128, leaf_capacity=64)
+    assert b > 2 ** 40 and 1.9 < b / a < 2.1
+    assert b > top * 128 * 8  # the result rows alone
+    with pytest.raises(binding.MknnError):
+        binding.footprint(n_max=2 ** 31, k_max=8)
+    with pytest.raises(binding.MknnError):
+        binding.footprint(n_max=1000, k_max=129)

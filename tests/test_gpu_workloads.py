@@ -64,3 +64,23 @@ def test_mixed_16m_k128_sampled():
     bi, bd, bc, _ = oracle.brute_knn(x, y, issuers=sample, k=k, threads=16)
     assert np.array_equal(gc, bc)
     assert np.array_equal(gi, bi) and np.array_equal(bits(gd), bits(bd))
+
+
+def test_maximum_size_64m_sampled():
+    """64M objects (positions on the device), k = 8: the largest snapshot the
+    tests build; rows checked against brute force on a sample."""
+    n = 64_000_000
+    rng = np.random.default_rng(77)
+    dx = torch.rand(n, generator=torch.Generator().manual_seed(5)).cuda()
+    dy = torch.rand(n, generator=torch.Generator().manual_seed(6)).cuda()
+    x, y = dx.cpu().numpy(), dy.cpu().numpy()
+    print("maximum size: %d objects" % n, flush=True)
+    with binding.Context(n, n, 8, leaf_capacity=32) as c:
+        c.load_positions(dx, dy)
+        c.advance_tick()
+        c.query(k=8)
+        sample = np.sort(rng.choice(n, 100, replace=False)).astype(np.int32)
+        gi, gd, gc = c.fetch_rows(sample, 8)
+    bi, bd, bc, _ = oracle.brute_knn(x, y, issuers=sample, k=8, threads=16)
+    assert np.array_equal(gc, bc)
+    assert np.array_equal(gi, bi) and np.array_equal(bits(gd), bits(bd))
