@@ -206,26 +206,26 @@ __device__ __forceinline__ void oddeven_sort(uint64_t (&b)[N])
     oddeven_apply<N>(b, std::make_integer_sequence<int, OddEven<N>::net.count>{});
 }
 
-template <int N, int STRIDE, int I>
+template <int N, int OFF, int STRIDE, int I>
 __device__ __forceinline__ void merge_ce(uint64_t (&a)[N])
 {
     constexpr int J = I ^ STRIDE;
-    if constexpr (J > I) cmp_swap(a[I], a[J]);
+    if constexpr (J > I) cmp_swap(a[OFF + I], a[OFF + J]);
 }
 
-template <int N, int STRIDE, int... I>
+template <int N, int OFF, int STRIDE, int... I>
 __device__ __forceinline__ void merge_stage(uint64_t (&a)[N], std::integer_sequence<int, I...>)
 {
-    (merge_ce<N, STRIDE, I>(a), ...);
+    (merge_ce<N, OFF, STRIDE, I>(a), ...);
 }
 
-// Sort a bitonic register array ascending (half-cleaner cascade).
-template <int N, int STRIDE = N / 2>
+// Sort the bitonic run a[OFF .. OFF+LEN) ascending (half-cleaner cascade).
+template <int N, int OFF = 0, int LEN = N, int STRIDE = LEN / 2>
 __device__ __forceinline__ void bitonic_merge(uint64_t (&a)[N])
 {
     if constexpr (STRIDE > 0) {
-        merge_stage<N, STRIDE>(a, std::make_integer_sequence<int, N>{});
-        bitonic_merge<N, STRIDE / 2>(a);
+        merge_stage<N, OFF, STRIDE>(a, std::make_integer_sequence<int, LEN>{});
+        bitonic_merge<N, OFF, LEN, STRIDE / 2>(a);
     }
 }
 
@@ -297,7 +297,22 @@ struct Selector {
         oddeven_sort<P>(b);
 #pragma unroll
         for (int i = K - P; i < K; ++i) a[i] = key_min(a[i], b[K - 1 - i]);
-        bitonic_merge<K>(a);
+        if constexpr (K == 2 * P) {
+            // a[P .. K) is now bitonic and holds the P smallest of the old
+            // upper half and the queue; the whole list is bitonic, and the
+            // bitonic merge is its first half-cleaner stage followed by
+            // independent merges of the two halves.  If no lane's smallest
+            // queued key is below a[P-1], the upper half is already no lower
+            // than the lower half: the first stage and the lower merge change
+            // nothing and are skipped.
+            if (wave_any(key_less(b[0], a[P - 1]))) {
+                merge_stage<K, 0, P>(a, std::make_integer_sequence<int, K>{});
+                bitonic_merge<K, 0, P>(a);
+            }
+            bitonic_merge<K, P, P>(a);
+        } else {
+            bitonic_merge<K>(a);
+        }
         cnt = 0;
         thr = key_min(a[K - 1], cap);
     }
