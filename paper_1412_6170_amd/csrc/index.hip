@@ -666,6 +666,8 @@ __global__ __launch_bounds__(kScanThreads) void k_leaves(
     }
 }
 
+constexpr uint32_t kLeafNodeGroups = 64;
+
 // Leaf level, and the nodes each leaf contributes to the depth-first
 // tables: its inner ancestors below the deepest quadrant it shares with the
 // previous leaf (forward) or next leaf (backward), then itself.  Both node
@@ -682,60 +684,66 @@ __global__ __launch_bounds__(kScanThreads) void k_leaf_nodes(
 {
     __shared__ uint32_t s_excl[2];
     const uint32_t nl = ctr->n_leaves;
-    const uint32_t tile = take_ticket(spf.ticket);
-    const uint32_t base = tile * (uint32_t)kScanTile;
-    if (base >= nl) return;
-    const uint32_t mine = base + threadIdx.x * (uint32_t)kScanItems;
-    uint32_t cf[kScanItems], cr[kScanItems], sf = 0, sr = 0;
     int deepest = 0;
+    // A small fixed grid takes tiles in ticket order until it passes the
+    // leaves (their count is only known here): a grid sized for the worst
+    // case would spend more time launching idle workgroups than working.
+    for (;;) {
+        const uint32_t tile = take_ticket(spf.ticket);
+        const uint32_t base = tile * (uint32_t)kScanTile;
+        if (base >= nl) break;
+        const uint32_t mine = base + threadIdx.x * (uint32_t)kScanItems;
+        uint32_t cf[kScanItems], cr[kScanItems], sf = 0, sr = 0;
 #pragma unroll
-    for (int j = 0; j < kScanItems; ++j) {
-        const uint32_t p = mine + j;
-        cf[j] = cr[j] = 0;
-        if (p < nl) {
-            const int32_t b = leaf_begin[p], e = leaf_end[p];
-            const int cl = b > 0 ? common_level(codes[b - 1], codes[b]) : -1;
-            const int crl = (uint32_t)e < n ? common_level(codes[e - 1], codes[e]) : -1;
-            const int lev = (e - b <= th) ? max(cl, crl) + 1 : L;
-            leaf_level[p] = lev;
-            leaf_code[p] = codes[b];
-            cf[j] = (uint32_t)(lev - cl);
-            cr[j] = (uint32_t)(lev - crl);
-            deepest = max(deepest, lev);
+        for (int j = 0; j < kScanItems; ++j) {
+            const uint32_t p = mine + j;
+            cf[j] = cr[j] = 0;
+            if (p < nl) {
+                const int32_t b = leaf_begin[p], e = leaf_end[p];
+                const int cl = b > 0 ? common_level(codes[b - 1], codes[b]) : -1;
+                const int crl = (uint32_t)e < n ? common_level(codes[e - 1], codes[e]) : -1;
+                const int lev = (e - b <= th) ? max(cl, crl) + 1 : L;
+                leaf_level[p] = lev;
+                leaf_code[p] = codes[b];
+                cf[j] = (uint32_t)(lev - cl);
+                cr[j] = (uint32_t)(lev - crl);
+                deepest = max(deepest, lev);
+            }
+            sf += cf[j];
+            sr += cr[j];
         }
-        sf += cf[j];
-        sr += cr[j];
-    }
-    uint32_t agg_f, agg_r;
-    uint32_t pre_f = block_excl_scan<kScanThreads>(sf, &agg_f);
-    __syncthreads();  // the scan's shared partials are reused below
-    uint32_t pre_r = block_excl_scan<kScanThreads>(sr, &agg_r);
-    if (threadIdx.x == 0) {
-        lb_publish(spf.status, 1, tile, agg_f);
-        lb_publish(spr.status, 1, tile, agg_r);
-    }
-    if (threadIdx.x < kWave) {
-        const uint64_t e = lb_resolve_wave(spf.status, tile, agg_f, spf.err, spf.epoch);
+        uint32_t agg_f, agg_r;
+        uint32_t pre_f = block_excl_scan<kScanThreads>(sf, &agg_f);
+        __syncthreads();  // the scan's shared partials are reused below
+        uint32_t pre_r = block_excl_scan<kScanThreads>(sr, &agg_r);
         if (threadIdx.x == 0) {
-            s_excl[0] = (uint32_t)e;
-            if (base + kScanTile >= nl) ctr->n_nodes = (uint32_t)e + agg_f;
+            lb_publish(spf.status, 1, tile, agg_f);
+            lb_publish(spr.status, 1, tile, agg_r);
         }
-    } else if (threadIdx.x < 2 * kWave) {
-        const uint64_t e = lb_resolve_wave(spr.status, tile, agg_r, spr.err, spr.epoch);
-        if (threadIdx.x == kWave) s_excl[1] = (uint32_t)e;
-    }
-    __syncthreads();
-    pre_f += s_excl[0];
-    pre_r += s_excl[1];
+        if (threadIdx.x < kWave) {
+            const uint64_t e = lb_resolve_wave(spf.status, tile, agg_f, spf.err, spf.epoch);
+            if (threadIdx.x == 0) {
+                s_excl[0] = (uint32_t)e;
+                if (base + kScanTile >= nl) ctr->n_nodes = (uint32_t)e + agg_f;
+            }
+        } else if (threadIdx.x < 2 * kWave) {
+            const uint64_t e = lb_resolve_wave(spr.status, tile, agg_r, spr.err, spr.epoch);
+            if (threadIdx.x == kWave) s_excl[1] = (uint32_t)e;
+        }
+        __syncthreads();
+        pre_f += s_excl[0];
+        pre_r += s_excl[1];
 #pragma unroll
-    for (int j = 0; j < kScanItems; ++j) {
-        const uint32_t p = mine + j;
-        if (p < nl) {
-            off_f[p] = pre_f;
-            off_r[p] = pre_r;
+        for (int j = 0; j < kScanItems; ++j) {
+            const uint32_t p = mine + j;
+            if (p < nl) {
+                off_f[p] = pre_f;
+                off_r[p] = pre_r;
+            }
+            pre_f += cf[j];
+            pre_r += cr[j];
         }
-        pre_f += cf[j];
-        pre_r += cr[j];
+        __syncthreads();  // s_excl and the scan partials are reused by the next tile
     }
     // Statistic only: one atomic per wavefront that saw leaves.
 #pragma unroll
@@ -985,7 +993,8 @@ void launch_build_index(IndexBuffers &b, const float *x, const float *y, int64_t
     const uint32_t ns = (uint32_t)((n + kScanTile - 1) / kScanTile);
     k_leaves<<<ns, kScanThreads, 0, s>>>(codes, nn, th, L, steps, b.scan[0], b.ctr, b.leaf_of,
                                          b.leaf_begin, b.leaf_end);
-    k_leaf_nodes<<<ns, kScanThreads, 0, s>>>(codes, nn, th, L, b.leaf_begin, b.leaf_end, b.scan[1],
+    const uint32_t gl = ns < kLeafNodeGroups ? ns : kLeafNodeGroups;
+    k_leaf_nodes<<<gl, kScanThreads, 0, s>>>(codes, nn, th, L, b.leaf_begin, b.leaf_end, b.scan[1],
                                              b.scan[2], b.ctr, b.leaf_level, b.leaf_code, b.cnt_f,
                                              b.cnt_r, epoch);
     const uint32_t gn = (uint32_t)((n + T / kLevelLanes - 1) / (T / kLevelLanes));
