@@ -128,6 +128,20 @@ def cpu_baseline(w, host_ticks):
                       "queries in all, %.1f s" % (done, w.name, len(host_ticks), queries, dt)}
 
 
+def copy_calibration():
+    """A plain 256 MiB device copy, repeated: what FETCH_SIZE and WRITE_SIZE
+    read for it scales those counters to bytes for the query kernel."""
+    import torch
+    torch.cuda.set_device(0)
+    src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": src.numel() * 4,
+                      "repeats": 5}), flush=True)
+
+
 def serving_bench(args):
     """Many independent scenes served with continuous batching: scene sizes
     log-uniform in [10k, 2M] objects, k in {8, 32}, tick requests arriving as

@@ -674,7 +674,7 @@ constexpr uint32_t kLeafNodeGroups = 64;
 // counts are scanned in the same pass (two look-back chains, resolved by
 // two wavefronts side by side) into the leaves' first node positions; the
 // last tile writes the node count.  Leaves are counted on the device, so
-// the grid covers every position and tiles past the leaves exit.
+// the workgroups loop over tiles until they pass the last leaf.
 __global__ __launch_bounds__(kScanThreads) void k_leaf_nodes(
     const uint32_t *__restrict__ codes, uint32_t n, int th, int L,
     const int32_t *__restrict__ leaf_begin, const int32_t *__restrict__ leaf_end, ScanSpace spf,

@@ -1,0 +1,56 @@
+"""CPU: bench.py's host logic -- every global name its functions load is
+defined (a mode whose handler was lost fails here, not on the GPU), the
+multi-GPU refusal, and the byte accounting of the roofline entry."""
+import builtins
+import dis
+import os
+import subprocess
+import sys
+import types
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def _global_loads(code):
+    for ins in dis.get_instructions(code):
+        if ins.opname == "LOAD_GLOBAL":
+            yield ins.argval
+    for c in code.co_consts:
+        if isinstance(c, types.CodeType):
+            yield from _global_loads(c)
+
+
+def test_every_global_name_is_defined():
+    missing = set()
+    for name, obj in vars(bench).items():
+        if isinstance(obj, types.FunctionType) and obj.__module__ == "bench":
+            for g in _global_loads(obj.__code__):
+                if not hasattr(bench, g) and not hasattr(builtins, g):
+                    missing.add((name, g))
+    assert not missing, sorted(missing)
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_query_kernel_bytes():
+    # 12 B per object read once, 8 k + 4 B per query written.
+    assert bench.query_kernel_bytes(1_000_000, 1_000_000, 32_000_000) == 12_000_000 + 260_000_000
+
+
+@pytest.mark.parametrize("workload", ["clustered_1m", "uniform_10k"])
+def test_traffic_only_for_matching_sources(workload):
+    m = bench.MEASURED_TRAFFIC
+    got = bench.measured_traffic(workload, m["leaf_capacity"])
+    if workload != m["workload"] or m["digest"] != bench.query_source_digest():
+        assert got is None
+    else:
+        assert got == m["fetch_bytes"] + m["write_bytes"]
