@@ -74,7 +74,11 @@ extern "C" {
 #define MKNN_K_LIMIT 128
 
 /* mknn_config.flags */
-#define MKNN_FLAG_TIMING 1   /* record per-phase device times (mknn_stats) */
+/* Record per-phase device times (mknn_stats): HIP events on the context's
+ * stream around each build and query, up to four per tick, recorded without
+ * a system-scope fence (timing only, so they cost the kernels around them
+ * next to nothing). */
+#define MKNN_FLAG_TIMING 1
 #define MKNN_FLAG_COUNTERS 2 /* count the query kernel's work (mknn_stats) */
 /* Variable-k queries: group the queries by the size class of their k
  * (lists of 8, 16, 32, 64, 128 keys) and answer each class with its own

@@ -51,13 +51,17 @@ struct mknn_ctx {
     int32_t *out_cnt = nullptr;
     unsigned long long *counters = nullptr;  // query-kernel work counters [5]
 
-    hipEvent_t ev[6]{};
-    bool have_events = false;
-    // Rings of event pairs for per-tick means: [slot][0..5] as ev above.
+    // Timing (MKNN_FLAG_TIMING): one ring slot of events per build and per
+    // query, [0] build start, [1] build end, [2] query start, [3] start of
+    // the leaf-sweep kernel, [4] query end.  [3] is not recorded when no
+    // preparation work precedes the kernel (then [2] stands for it).
     static constexpr int kRing = 256;
-    hipEvent_t ring[kRing][6]{};
+    static constexpr int kMarks = 5;
+    hipEvent_t ring[kRing][kMarks]{};
+    bool main_is_start[kRing]{};
     bool have_ring = false;
-    int64_t ring_build = 0, ring_query = 0;   // calls recorded since reset
+    int64_t builds_timed = 0, queries_timed = 0;  // since the last reset
+    int64_t build_slot = 0, query_slot = 0;       // calls ever recorded
     std::vector<void *> allocs;
 };
 
@@ -252,16 +256,23 @@ void configure(mknn_ctx *c, const mknn_config *cfg)
 }
 
 
-// Record event i (0..5, same meaning as mknn_ctx::ev) for timing.
+// Record timing mark i (0..4, as mknn_ctx::ring) in the current build's or
+// query's ring slot.
 int mark(mknn_ctx *c, int i)
 {
-    if (!((c->cfg.flags & MKNN_FLAG_TIMING) && c->have_events)) return MKNN_OK;
-    HIP_OR_FAIL(c, hipEventRecord(c->ev[i], c->stream));
-    if (c->have_ring) {
-        const int64_t slot = (i < 2 ? c->ring_build : c->ring_query) % mknn_ctx::kRing;
-        HIP_OR_FAIL(c, hipEventRecord(c->ring[slot][i], c->stream));
-    }
+    if (!((c->cfg.flags & MKNN_FLAG_TIMING) && c->have_ring)) return MKNN_OK;
+    const int64_t slot = (i < 2 ? c->build_slot : c->query_slot) % mknn_ctx::kRing;
+    HIP_OR_FAIL(c, hipEventRecord(c->ring[slot][i], c->stream));
     return MKNN_OK;
+}
+
+// Start of the leaf-sweep kernel: a mark of its own only if preparation
+// work was enqueued since the query started.
+int mark_main(mknn_ctx *c, bool prepared)
+{
+    if (!((c->cfg.flags & MKNN_FLAG_TIMING) && c->have_ring)) return MKNN_OK;
+    c->main_is_start[c->query_slot % mknn_ctx::kRing] = !prepared;
+    return prepared ? mark(c, 3) : MKNN_OK;
 }
 
 }  // namespace
@@ -300,8 +311,6 @@ int mknn_destroy(mknn_ctx *c)
     (void)hipSetDevice(c->cfg.device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     for (void *p : c->allocs) (void)hipFree(p);
-    if (c->have_events)
-        for (auto &e : c->ev) (void)hipEventDestroy(e);
     for (auto &slot : c->ring)
         for (auto &e : slot)
             if (e) (void)hipEventDestroy(e);
@@ -359,14 +368,14 @@ int mknn_create(const mknn_config *cfg, mknn_ctx **out)
         if (!rc) rc = dalloc(c, &p, count);
     });
     if (!rc) {
-        c->have_events = true;
-        for (auto &ev : c->ev)
-            if (hipEventCreate(&ev) != hipSuccess) c->have_events = false;
         if (cfg->flags & MKNN_FLAG_TIMING) {
+            // Timing only: no system-scope fence when an event is recorded
+            // (its cache writeback would cost the following kernels time).
             c->have_ring = true;
             for (auto &slot : c->ring)
                 for (auto &ev : slot)
-                    if (hipEventCreate(&ev) != hipSuccess) c->have_ring = false;
+                    if (hipEventCreateWithFlags(&ev, hipEventDisableSystemFence) != hipSuccess)
+                        c->have_ring = false;
         }
         k_reset_counters<<<1, 1, 0, c->stream>>>(c->ix.ctr);
         k_zero_u64<<<1, 8, 0, c->stream>>>(c->counters, 8);
@@ -432,7 +441,8 @@ int mknn_advance_tick(mknn_ctx *c)
     rc = check_launch(c, "index build");
     if (!rc) rc = mark(c, 1);
     if (rc) return rc;
-    ++c->ring_build;
+    ++c->build_slot;
+    ++c->builds_timed;
     c->ticked = true;
     c->queried = false;
     c->inv_ready = false;
@@ -459,7 +469,8 @@ int mknn_refit_tick(mknn_ctx *c)
     rc = check_launch(c, "refit");
     if (!rc) rc = mark(c, 1);
     if (rc) return rc;
-    ++c->ring_build;
+    ++c->build_slot;
+    ++c->builds_timed;
     c->ticked = true;
     c->queried = false;
     ++c->refits;
@@ -500,7 +511,8 @@ QueryArgs base_query_args(mknn_ctx *c, int64_t nq, const int32_t *ks, int32_t k_
 // Host-side description of the results of the query just enqueued.
 void record_query(mknn_ctx *c, int64_t nq, const int32_t *ks, int32_t k_uniform, int32_t where)
 {
-    ++c->ring_query;
+    ++c->query_slot;
+    ++c->queries_timed;
     c->queried = true;
     c->nq = nq;
     c->var_k = ks != nullptr;
@@ -622,12 +634,11 @@ int mknn_query_points(mknn_ctx *c, const float *qx, const float *qy, const int32
         launch_zero_words(c->qws.base, words, c->stream);
         launch_offsets(c->kcount, 0, c->kscan, c->qscan, c->ktotal, c->offsets, c->stream);
     }
-    rc = mark(c, 4);
+    rc = mark_main(c, nq > 0 || ks != nullptr);
     if (rc) return rc;
     launch_knn(qa, k_class(kmax_call), c->stream);
     rc = check_launch(c, "k-NN query");
-    if (!rc) rc = mark(c, 5);
-    if (!rc) rc = mark(c, 3);
+    if (!rc) rc = mark(c, 4);
     if (rc) return rc;
     record_query(c, nq, ks, k_uniform, where);
     return MKNN_OK;
@@ -744,7 +755,7 @@ int mknn_query(mknn_ctx *c, const int32_t *issuers, const int32_t *ks, int64_t n
         launch_zero_words(c->qws.base, words, c->stream);
         launch_offsets(c->kcount, 0, c->kscan, c->qscan, c->ktotal, c->offsets, c->stream);
     }
-    rc = mark(c, 4);
+    rc = mark_main(c, issuers != nullptr || ks != nullptr);
     if (rc) return rc;
     if (qa.class_bounds) {
         const int top = class_slot(kmax_call);
@@ -757,8 +768,7 @@ int mknn_query(mknn_ctx *c, const int32_t *issuers, const int32_t *ks, int64_t n
         launch_knn(qa, k_class(kmax_call), c->stream);
     }
     rc = check_launch(c, "k-NN query");
-    if (!rc) rc = mark(c, 5);
-    if (!rc) rc = mark(c, 3);
+    if (!rc) rc = mark(c, 4);
     if (rc) return rc;
     record_query(c, nq, ks, k_uniform, where);
     return MKNN_OK;
@@ -896,8 +906,8 @@ int mknn_reset_timing(mknn_ctx *c)
     if (!c) return MKNN_E_INVAL;
     int rc = mknn_sync(c);
     if (rc) return rc;
-    c->ring_build = 0;
-    c->ring_query = 0;
+    c->builds_timed = 0;
+    c->queries_timed = 0;
     k_zero_u64<<<1, 8, 0, c->stream>>>(c->counters, 8);
     return check_launch(c, "reset counters");
 }
@@ -932,30 +942,39 @@ int mknn_get_stats(const mknn_ctx *cc, mknn_stats *out)
             const uint32_t bits = (uint32_t)h.drift;
             memcpy(&out->drift, &bits, sizeof bits);
         }
-        if ((c->cfg.flags & MKNN_FLAG_TIMING) && c->have_events) {
+        if ((c->cfg.flags & MKNN_FLAG_TIMING) && c->have_ring) {
+            const int R = mknn_ctx::kRing;
             float ms = 0;
-            if (hipEventElapsedTime(&ms, c->ev[0], c->ev[1]) == hipSuccess) out->ms_build = ms;
-            if (c->queried) {
-                if (hipEventElapsedTime(&ms, c->ev[2], c->ev[3]) == hipSuccess) out->ms_query = ms;
-                if (hipEventElapsedTime(&ms, c->ev[4], c->ev[5]) == hipSuccess)
-                    out->ms_query_main = ms;
+            auto elapsed = [&](int64_t slot, int a, int b, double *acc) {
+                hipEvent_t ea = c->ring[slot % R][a], eb = c->ring[slot % R][b];
+                if (a == 3 && c->main_is_start[slot % R]) ea = c->ring[slot % R][2];
+                if (hipEventElapsedTime(&ms, ea, eb) != hipSuccess) return false;
+                *acc += ms;
+                return true;
+            };
+            double v = 0;
+            if (c->build_slot > 0 && elapsed(c->build_slot - 1, 0, 1, &v)) out->ms_build = (float)v;
+            if (c->queried && c->query_slot > 0) {
+                v = 0;
+                if (elapsed(c->query_slot - 1, 2, 4, &v)) out->ms_query = (float)v;
+                v = 0;
+                if (elapsed(c->query_slot - 1, 3, 4, &v)) out->ms_query_main = (float)v;
             }
-            if (c->have_ring) {
-                const int64_t nb = c->ring_build < mknn_ctx::kRing ? c->ring_build : mknn_ctx::kRing;
-                const int64_t nqr = c->ring_query < mknn_ctx::kRing ? c->ring_query : mknn_ctx::kRing;
-                double sb = 0, sq = 0, sm = 0;
-                for (int64_t i = 0; i < nb; ++i)
-                    if (hipEventElapsedTime(&ms, c->ring[i][0], c->ring[i][1]) == hipSuccess) sb += ms;
-                for (int64_t i = 0; i < nqr; ++i) {
-                    if (hipEventElapsedTime(&ms, c->ring[i][2], c->ring[i][3]) == hipSuccess) sq += ms;
-                    if (hipEventElapsedTime(&ms, c->ring[i][4], c->ring[i][5]) == hipSuccess) sm += ms;
-                }
-                out->timed_ticks = (int32_t)(nb < nqr ? nb : nqr);
-                if (nb) out->ms_build_mean = (float)(sb / nb);
-                if (nqr) {
-                    out->ms_query_mean = (float)(sq / nqr);
-                    out->ms_query_main_mean = (float)(sm / nqr);
-                }
+            // Means over the builds and queries since the last reset (at
+            // most the ring's length, the most recent ones).
+            const int64_t nb = c->builds_timed < R ? c->builds_timed : R;
+            const int64_t nqr = c->queries_timed < R ? c->queries_timed : R;
+            double sb = 0, sq = 0, sm = 0;
+            for (int64_t i = 0; i < nb; ++i) elapsed(c->build_slot - 1 - i, 0, 1, &sb);
+            for (int64_t i = 0; i < nqr; ++i) {
+                elapsed(c->query_slot - 1 - i, 2, 4, &sq);
+                elapsed(c->query_slot - 1 - i, 3, 4, &sm);
+            }
+            out->timed_ticks = (int32_t)(nb < nqr ? nb : nqr);
+            if (nb) out->ms_build_mean = (float)(sb / nb);
+            if (nqr) {
+                out->ms_query_mean = (float)(sq / nqr);
+                out->ms_query_main_mean = (float)(sm / nqr);
             }
             (void)hipGetLastError();
         }

@@ -1,0 +1,84 @@
+"""GPU: per-phase device times (MKNN_FLAG_TIMING).  The build, the whole
+query and its leaf-sweep kernel are timed from HIP events on the context's
+stream; the statistics must be positive, ordered (the kernel is part of the
+query) and averaged over exactly the ticks since the last reset.  Results
+with timing on are the same as with timing off."""
+import numpy as np
+import pytest
+
+from paper_1412_6170_amd import binding, workloads
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    torch.cuda.set_device(0)
+    yield
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def run(ctx, x, y, k, issuers=None, ks=None):
+    ctx.load_positions(torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda())
+    ctx.advance_tick()
+    if issuers is None:
+        ctx.query(k=k, nq=len(x))
+    else:
+        ctx.query(issuers=torch.from_numpy(issuers).cuda(),
+                  ks=None if ks is None else torch.from_numpy(ks).cuda())
+    return ctx.fetch()
+
+
+@pytest.mark.parametrize("subset", [False, True])
+def test_times_positive_ordered_and_counted(subset):
+    w = workloads.clustered_1m(n=100_000, ticks=5)
+    k = 16
+    n = w.n
+    rng = np.random.default_rng(5)
+    say("timing: subset=%s n=%d" % (subset, n))
+    with binding.Context(n, n, k, timing=True) as ct, binding.Context(n, n, k) as cp:
+        ct.reset_timing()
+        for t in range(5):
+            x, y, _, _, _ = w.tick(t)
+            iss = ks = None
+            if subset:
+                iss = rng.permutation(n)[: n // 3].astype(np.int32)
+                ks = rng.integers(1, k + 1, len(iss)).astype(np.int32)
+            a = run(ct, x, y, k, iss, ks)
+            b = run(cp, x, y, k, iss, ks)
+            for u, v in zip(a, b):
+                if u is not None:
+                    assert np.array_equal(np.asarray(u).view(np.uint8), np.asarray(v).view(np.uint8))
+        ct.sync()
+        st = ct.stats()
+        say(st)
+        assert st["timed_ticks"] == 5
+        assert st["ms_build"] > 0 and st["ms_query"] > 0 and st["ms_query_main"] > 0
+        assert st["ms_query_main"] <= st["ms_query"]
+        assert st["ms_build_mean"] > 0 and st["ms_query_mean"] > 0
+        assert 0 < st["ms_query_main_mean"] <= st["ms_query_mean"]
+        if subset:
+            # Query preparation (sort by position, row offsets) runs before
+            # the kernel, so the kernel is strictly part of the query.
+            assert st["ms_query_main"] < st["ms_query"]
+        ct.reset_timing()
+        x, y, _, _, _ = w.tick(0)
+        run(ct, x, y, k)
+        ct.sync()
+        assert ct.stats()["timed_ticks"] == 1
+
+
+def test_timing_off_reports_zero():
+    w = workloads.uniform_10k()
+    x, y, _, _, k = w.tick(0)
+    with binding.Context(len(x), len(x), k) as c:
+        run(c, x, y, k)
+        c.sync()
+        st = c.stats()
+        assert st["ms_build"] == 0 and st["ms_query_main"] == 0 and st["timed_ticks"] == 0
