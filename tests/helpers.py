@@ -61,6 +61,34 @@ def sq_dist_np(qx, qy, px, py):
     return dx * dx + dy * dy
 
 
+def check_rows_vectorized(x, y, issuers, ids, d2, counts, k):
+    """The per-row invariants of check_invariants for a block of uniform-k
+    rows, vectorized (no mutual-consistency check, which needs every row):
+    count = min(k, n-1), padding, ids in range, no self, no duplicates,
+    d2 bit-equal to the fp32 d2 recomputed for each id, keys strictly
+    ascending."""
+    x, y = f32(x), f32(y)
+    n = len(x)
+    s = np.asarray(issuers, np.int64)
+    c = np.asarray(counts)
+    assert np.all(c == min(k, n - 1))
+    col = np.arange(k)[None, :]
+    real = col < c[:, None]
+    assert np.all(ids[~real] == -1) and np.all(np.isinf(d2[~real]))
+    vi = np.where(real, ids, 0).astype(np.int64)
+    assert np.all((vi >= 0) & (vi < n))
+    assert not np.any(real & (vi == s[:, None]))
+    dx = x[s][:, None] - x[vi]
+    dy = y[s][:, None] - y[vi]
+    rec = dx * dx + dy * dy
+    assert rec.dtype == np.float32
+    assert np.array_equal(np.where(real, rec, np.inf).view(np.uint32),
+                          np.where(real, d2, np.inf).view(np.uint32))
+    keys = (d2.view(np.uint32).astype(np.uint64) << np.uint64(32)) | vi.astype(np.uint64)
+    inc = keys[:, 1:] > keys[:, :-1]
+    assert np.all(inc | ~real[:, 1:])  # strictly ascending, hence no duplicates
+
+
 def check_invariants(x, y, issuers, ks, ids, d2, counts, offsets=None, k=None):
     """Properties every exact result satisfies, for all queries:
     count = min(k, n-1); rows strictly ascending by (d2, id); no self, no

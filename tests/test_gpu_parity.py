@@ -90,11 +90,12 @@ def test_uniform_10k_full_parity():
 
 def test_clustered_1m_all_ticks_full_parity():
     """The benchmark's 1M-object workload, every tick, every query, in the
-    configuration bench.py times (automatic leaf capacity, one context
-    advanced tick after tick)."""
+    configuration bench.py times (leaf capacity 64, one context advanced
+    tick after tick): the whole result against the oracle, and
+    2,000 sampled queries per tick against brute force."""
     w = workloads.clustered_1m()
     k = w.k
-    with binding.Context(w.n, w.n, k) as c:
+    with binding.Context(w.n, w.n, k, leaf_capacity=64, k_hint=k) as c:
         for t in range(w.ticks):
             x, y, _, _, _ = w.tick(t)
             say("clustered_1m tick %d" % t)
@@ -104,11 +105,12 @@ def test_clustered_1m_all_ticks_full_parity():
             got = c.fetch()
             exp = oracle.knn(x, y, k=k, threads=16)
             assert_rows_equal(got, exp, "tick %d" % t)
-            if t == 0:
-                rng = np.random.default_rng(11)
-                sample = rng.choice(w.n, 200, replace=False).astype(np.int32)
-                bi, bd, bc, _ = oracle.brute_knn(x, y, issuers=sample, k=k, threads=16)
-                assert same(got[0][sample], bi) and same_bits(got[1][sample], bd)
+            # The oracle itself checked against brute force on 2,000 queries.
+            rng = np.random.default_rng(11 + t)
+            sample = rng.choice(w.n, 2000, replace=False).astype(np.int32)
+            bi, bd, bc, _ = oracle.brute_knn(x, y, issuers=sample, k=k, threads=16)
+            assert same(got[0][sample], bi) and same_bits(got[1][sample], bd)
+            assert np.array_equal(got[2][sample], bc)
 
 
 # ---------------------------------------------------------------------------

@@ -1,0 +1,49 @@
+"""CPU: the vectorized per-row invariant check used on the largest GPU
+workloads accepts the oracle's exact answer and rejects planted mistakes
+(a swapped pair, a d2 off by one ulp, the issuer in its own row, a
+duplicate, a wrong count)."""
+import numpy as np
+import pytest
+
+import oracle
+from tests.helpers import check_rows_vectorized, family
+
+
+@pytest.fixture(scope="module")
+def exact():
+    x, y = family("clustered", 1500, 3)
+    k = 16
+    ids, d2, cnt, _ = oracle.knn(x, y, k=k, th=32)
+    return x, y, k, ids, d2, cnt
+
+
+def test_accepts_the_exact_answer(exact):
+    x, y, k, ids, d2, cnt = exact
+    check_rows_vectorized(x, y, np.arange(len(x)), ids, d2, cnt, k)
+    check_rows_vectorized(x, y, np.arange(100, 400), ids[100:400], d2[100:400], cnt[100:400], k)
+
+
+def plant(exact, how):
+    x, y, k, ids, d2, cnt = exact
+    ids, d2, cnt = ids.copy(), d2.copy(), cnt.copy()
+    r = 77
+    if how == "swap":
+        ids[r, [3, 4]] = ids[r, [4, 3]]
+        d2[r, [3, 4]] = d2[r, [4, 3]]
+    elif how == "ulp":
+        d2[r, 5] = np.nextafter(d2[r, 5], np.float32(np.inf))
+    elif how == "self":
+        ids[r, k - 1] = r
+    elif how == "dup":
+        ids[r, 6] = ids[r, 5]
+        d2[r, 6] = d2[r, 5]
+    elif how == "count":
+        cnt[r] -= 1
+    return x, y, k, ids, d2, cnt
+
+
+@pytest.mark.parametrize("how", ["swap", "ulp", "self", "dup", "count"])
+def test_rejects_planted_mistakes(exact, how):
+    x, y, k, ids, d2, cnt = plant(exact, how)
+    with pytest.raises(AssertionError):
+        check_rows_vectorized(x, y, np.arange(len(x)), ids, d2, cnt, k)
