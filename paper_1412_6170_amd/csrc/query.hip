@@ -734,7 +734,7 @@ void launch_knn(const QueryArgs &qa, int kclass, hipStream_t s)
     case 16: k_knn_tiles<16, 16><<<grid, block, 0, s>>>(qa); break;
     case 32: k_knn_tiles<32, 16><<<grid, block, 0, s>>>(qa); break;
     case 64: k_knn_tiles<64, 32><<<grid, block, 0, s>>>(qa); break;
-    default: k_knn_tiles<128, 32><<<grid, block, 0, s>>>(qa); break;
+    default: k_knn_tiles<128, 64><<<grid, block, 0, s>>>(qa); break;
     }
 }
 
