@@ -589,16 +589,42 @@ void launch_inverse(const IndexBuffers &b, int64_t n, hipStream_t s)
 // are independent and in flight together), scans the flags in one pass
 // with decoupled look-back, and writes the leaf of every position and the
 // [begin, end) range of every leaf; the last tile writes the leaf count.
+// The searches of a tile read codes within th positions of it only: up to
+// kLeavesStageTh, that span is first copied to LDS with coalesced loads
+// and every search step reads LDS (Staged); beyond it, global memory.
+constexpr int kLeavesStageTh = 1024;
+constexpr int kLeavesSpan = kScanTile + 2 * kLeavesStageTh;
+
+// LDS slot of staged code i: one word of skew per 32, so lanes reading
+// positions kScanItems apart fall in different banks.
+__host__ __device__ constexpr int leaves_slot(int i) { return i + (i >> 5); }
+
+template <bool Staged>
 __global__ __launch_bounds__(kScanThreads) void k_leaves(
     const uint32_t *__restrict__ codes, uint32_t n, int th, int L, int search_steps, ScanSpace sp,
     IndexCounters *__restrict__ ctr, int32_t *__restrict__ leaf_of,
     int32_t *__restrict__ leaf_begin, int32_t *__restrict__ leaf_end)
 {
     __shared__ uint32_t s_excl;
+    __shared__ uint32_t s_codes[Staged ? leaves_slot(kLeavesSpan) : 1];
     const uint32_t tile = take_ticket(sp.ticket);
     const uint32_t base = tile * (uint32_t)kScanTile;
     if (base >= n) return;  // past the data; nobody waits on it
     const uint32_t mine = base + threadIdx.x * (uint32_t)kScanItems;
+
+    // Every position read below lies in [lo, hi): a pair's two codes, its
+    // search window [p - th, p - 1] and the test position, below p + th.
+    const int64_t lo = max((int64_t)base - th, (int64_t)0);
+    const int64_t hi = min((int64_t)base + kScanTile + th, (int64_t)n);
+    if constexpr (Staged) {
+        for (int64_t i = lo + threadIdx.x; i < hi; i += kScanThreads)
+            s_codes[leaves_slot((int)(i - lo))] = codes[i];
+        __syncthreads();
+    }
+    auto code_at = [&](int64_t i) -> uint32_t {
+        if constexpr (Staged) return s_codes[leaves_slot((int)(i - lo))];
+        else return codes[i];
+    };
 
     uint32_t a[kScanItems];
     int c[kScanItems];
@@ -607,20 +633,20 @@ __global__ __launch_bounds__(kScanThreads) void k_leaves(
     for (int j = 0; j < kScanItems; ++j) {
         const uint32_t p = mine + j;
         const bool pair = p >= 1 && p < n;
-        const uint32_t q = pair ? p - 1 : 0;
-        a[j] = codes[q];
-        const uint32_t b = pair ? codes[p] : a[j];
+        // Positions without a pair read (and search) nothing outside [lo, hi).
+        const int64_t q = pair ? (int64_t)p - 1 : lo;
+        a[j] = code_at(q);
+        const uint32_t b = pair ? code_at(p) : a[j];
         c[j] = pair ? common_level(a[j], b) : kCodeLevels;
-        first[j] = (int64_t)q + 1 - th;
-        if (first[j] < 0) first[j] = 0;
-        count[j] = (pair && c[j] < L) ? (int64_t)q - first[j] : 0;
+        first[j] = pair ? max(q + 1 - th, (int64_t)0) : lo;
+        count[j] = (pair && c[j] < L) ? q - first[j] : 0;
     }
     for (int step = 0; step < search_steps; ++step) {
 #pragma unroll
         for (int j = 0; j < kScanItems; ++j) {
             const int64_t half = count[j] >> 1;
             const int64_t mid = first[j] + half;
-            const bool out = count[j] > 0 && !same_quadrant(codes[mid], a[j], c[j]);
+            const bool out = count[j] > 0 && !same_quadrant(code_at(mid), a[j], c[j]);
             first[j] = out ? mid + 1 : first[j];
             count[j] = count[j] > 0 ? (out ? count[j] - half - 1 : half) : 0;
         }
@@ -632,7 +658,7 @@ __global__ __launch_bounds__(kScanThreads) void k_leaves(
         uint32_t split = 0;
         if (p >= 1 && p < n && c[j] < L) {
             const int64_t last = first[j] + th;
-            split = (last < (int64_t)n && same_quadrant(codes[last], a[j], c[j])) ? 1u : 0u;
+            split = (last < (int64_t)n && same_quadrant(code_at(last), a[j], c[j])) ? 1u : 0u;
         }
         f[j] = p == 0 ? 1u : split;
         f[j] = p < n ? f[j] : 0u;
@@ -991,8 +1017,12 @@ void launch_build_index(IndexBuffers &b, const float *x, const float *y, int64_t
     int steps = 1;
     while ((1ll << steps) <= (int64_t)th + 1) ++steps;
     const uint32_t ns = (uint32_t)((n + kScanTile - 1) / kScanTile);
-    k_leaves<<<ns, kScanThreads, 0, s>>>(codes, nn, th, L, steps, b.scan[0], b.ctr, b.leaf_of,
-                                         b.leaf_begin, b.leaf_end);
+    if (th <= kLeavesStageTh)
+        k_leaves<true><<<ns, kScanThreads, 0, s>>>(codes, nn, th, L, steps, b.scan[0], b.ctr,
+                                                   b.leaf_of, b.leaf_begin, b.leaf_end);
+    else
+        k_leaves<false><<<ns, kScanThreads, 0, s>>>(codes, nn, th, L, steps, b.scan[0], b.ctr,
+                                                    b.leaf_of, b.leaf_begin, b.leaf_end);
     const uint32_t gl = ns < kLeafNodeGroups ? ns : kLeafNodeGroups;
     k_leaf_nodes<<<gl, kScanThreads, 0, s>>>(codes, nn, th, L, b.leaf_begin, b.leaf_end, b.scan[1],
                                              b.scan[2], b.ctr, b.leaf_level, b.leaf_code, b.cnt_f,
