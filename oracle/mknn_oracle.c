@@ -21,9 +21,12 @@
  *   * oracle_brute_knn: that definition written out (every object is a
  *     candidate).  Pinned against closed forms and a numpy brute force.
  *   * oracle_build_index: the index of Sec. 4.1 -- Morton codes on the
- *     virtual full quadtree at level 16, a sort of the objects by (code, id),
- *     and the level-by-level PR-quadtree split of every quadrant holding more
- *     than th objects, up to the maximum level L (leaves at L may exceed th).
+ *     virtual full quadtree of height L (the maximum level; the level-L code
+ *     is the level-16 code without its 2(16-L) low bits), a sort of the
+ *     objects by (level-L code, id), and the level-by-level PR-quadtree split
+ *     of every quadrant holding more than th objects, up to level L (leaves
+ *     at L may exceed th).  The level-16 code of every object is kept: it
+ *     places the object in its quadrant at every level.
  *   * oracle_brute_knn_points / oracle_knn_points: the same two searches
  *     for queries q = (x, y, k) with a free centre in [0,1)^2 (Definition
  *     1) and an optional excluded object id.
@@ -162,15 +165,16 @@ static uint32_t ancestor(uint32_t code, int level)
 /* ------------------------------------------------------------------------ */
 
 typedef struct {
-    uint32_t code;
+    uint32_t code; /* level-16 code */
+    uint32_t key;  /* Morton code at the maximum level L: the sort key */
     int32_t id;
 } obj_ref;
 
 static int cmp_obj(const void *pa, const void *pb)
 {
     const obj_ref *a = (const obj_ref *)pa, *b = (const obj_ref *)pb;
-    if (a->code != b->code)
-        return a->code < b->code ? -1 : 1;
+    if (a->key != b->key)
+        return a->key < b->key ? -1 : 1;
     if (a->id != b->id)
         return a->id < b->id ? -1 : 1;
     return 0;
@@ -256,7 +260,7 @@ static int64_t build_node(node_vec *v, const obj_ref *objs, int level, uint32_t 
 
 typedef struct {
     int64_t n;
-    obj_ref *objs; /* sorted by (code, id) */
+    obj_ref *objs; /* sorted by (level-L code, id) */
     float *sx, *sy; /* positions in sorted order */
     node_vec tree;
 } qindex;
@@ -289,6 +293,7 @@ static int make_index(const float *x, const float *y, int64_t n, int th, int L, 
     }
     for (int64_t i = 0; i < n; ++i) {
         ix->objs[i].code = oracle_morton(x[i], y[i]);
+        ix->objs[i].key = ancestor(ix->objs[i].code, L);
         ix->objs[i].id = (int32_t)i;
     }
     qsort(ix->objs, (size_t)n, sizeof(obj_ref), cmp_obj);

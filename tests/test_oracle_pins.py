@@ -137,10 +137,15 @@ def _check_index(x, y, th, L):
     ix = oracle.build_index(x, y, th, L)
     n = len(x)
     codes, ids = ix["codes"], ix["ids"]
-    # Sorted by (code, id), and a permutation of the objects.
+    # A permutation of the objects, sorted by (Morton code at level L, id):
+    # the level-L code is the level-16 code without its 2(16-L) low bits.
     assert same(np.sort(ids), np.arange(n))
-    key = codes.astype(np.uint64) << np.uint64(32) | ids.astype(np.uint64)
+    lcode = codes.astype(np.uint64) >> np.uint64(2 * (16 - L))
+    key = lcode << np.uint64(32) | ids.astype(np.uint64)
     assert np.all(key[1:] > key[:-1])
+    if L == 16:
+        full = codes.astype(np.uint64) << np.uint64(32) | ids.astype(np.uint64)
+        assert np.all(full[1:] > full[:-1])
     # Leaves tile [0, n) in order and share their quadrant prefix.
     beg, end, lev, pre = ix["leaf_begin"], ix["leaf_end"], ix["leaf_level"], ix["leaf_prefix"]
     if n:
