@@ -43,6 +43,12 @@ TH_CANDIDATES = (16, 24, 32, 48, 64, 96, 128, 192)
 # Leaf capacity used when --autotune is not given: the autotuner's choice on
 # MI355X for each workload (device time per tick over TH_CANDIDATES).
 TUNED_LEAF_CAPACITY = {"clustered_1m": 64, "uniform_10k": 32, "network_4m": 64, "mixed_16m": 64}
+# Maximum quadtree level (l_max, Sec. 4.1) per workload; absent: 16.  The
+# build sorts only the top 2 * l_max bits of the Morton codes, so 12 saves a
+# radix pass; on clustered_1m at capacity 64 it leaves the query time
+# unchanged (a few level-13 leaves become larger level-12 leaves).  Results
+# never depend on it.
+TUNED_MAX_LEVEL = {"clustered_1m": 12}
 CPU_SAMPLE_SECONDS = 10.0
 
 # HBM bytes per launch of the query kernel on clustered_1m at the tuned leaf
@@ -266,6 +272,9 @@ def main():
     ap.add_argument("--ticks", type=int, default=0,
                     help="generate at most this many ticks and cycle over them (0: all, "
                          "but at most 10 for workloads above 2M objects)")
+    ap.add_argument("--max-level", type=int, default=0,
+                    help="maximum quadtree level 1..16; 0 = the tuned value for the workload %s "
+                         "(else 16)" % (TUNED_MAX_LEVEL,))
     ap.add_argument("--leaf-capacity", type=int, default=0,
                     help="leaf capacity; 0 = the tuned value for the workload %s"
                          % (TUNED_LEAF_CAPACITY,))
@@ -357,8 +366,10 @@ def main():
              else TH_CANDIDATES)
     th0 = (min(cands) if args.autotune else
            args.leaf_capacity or TUNED_LEAF_CAPACITY.get(w.name, 0))
-    ctx = binding.Context(n, nq_max, k, leaf_capacity=th0, k_hint=k, stream=stream.cuda_stream,
-                          timing=True, counters=args.counters, group_k=args.group_k)
+    max_level = args.max_level or TUNED_MAX_LEVEL.get(w.name, 16)
+    ctx = binding.Context(n, nq_max, k, leaf_capacity=th0, k_hint=k, max_level=max_level,
+                          stream=stream.cuda_stream, timing=True, counters=args.counters,
+                          group_k=args.group_k)
 
     def step(s):
         x, y = dev[s % n_ticks]
@@ -404,7 +415,8 @@ def main():
         "config": {"workload": w.name, "objects": n, "queries_per_tick": nq_mean,
                    "k": k if not subset else "per query, mean %.1f" % (entries_mean / nq_mean),
                    "ticks": w.ticks, "ticks_generated": n_ticks,
-                   "leaf_capacity": st["leaf_capacity"], "description": w.description},
+                   "leaf_capacity": st["leaf_capacity"], "max_level": max_level,
+                   "description": w.description},
         "p50_tick_ms": float(np.percentile(lat, 50)),
         "p99_tick_ms": float(np.percentile(lat, 99)),
         "device_ms_build_mean": st["ms_build_mean"],
@@ -436,7 +448,8 @@ def main():
         # The same ticks, each captured once as a HIP graph (one graph per
         # tick's input buffers) and replayed; no timing events inside.
         gctx = binding.Context(n, nq_max, k, leaf_capacity=out["config"]["leaf_capacity"],
-                               k_hint=k, stream=stream.cuda_stream, group_k=args.group_k)
+                               max_level=max_level, k_hint=k, stream=stream.cuda_stream,
+                               group_k=args.group_k)
 
         def gstep(s):
             x, y = dev[s % n_ticks]
@@ -470,7 +483,8 @@ def main():
         # queries.
         pstreams = [torch.cuda.Stream(), torch.cuda.Stream()]  # default priority
         pctx = [binding.Context(n, nq_max, k, leaf_capacity=out["config"]["leaf_capacity"],
-                                k_hint=k, stream=ps.cuda_stream, group_k=args.group_k)
+                                max_level=max_level, k_hint=k, stream=ps.cuda_stream,
+                                group_k=args.group_k)
                 for ps in pstreams]
 
         def pstep(s):
@@ -499,8 +513,8 @@ def main():
         # full build, else rebuild.  The policy reads the previous query's
         # device time each tick (a host wait inside the timed region).
         rctx = binding.Context(n, nq_max, k, leaf_capacity=out["config"]["leaf_capacity"],
-                               k_hint=k, stream=stream.cuda_stream, timing=True,
-                               group_k=args.group_k)
+                               max_level=max_level, k_hint=k, stream=stream.cuda_stream,
+                               timing=True, group_k=args.group_k)
         pol = binding.ReusePolicy(factor=args.reuse_factor)
 
         def rstep(s):

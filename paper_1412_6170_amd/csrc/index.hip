@@ -371,7 +371,7 @@ __device__ __forceinline__ uint64_t digit_peers(uint32_t d, uint64_t valid)
 }
 
 __global__ __launch_bounds__(kSortThreads) void k_radix_ghist(const uint32_t *__restrict__ keys,
-                                                             uint32_t n, int passes,
+                                                             uint32_t n, int passes, int low_bit,
                                                              uint32_t *__restrict__ ghist)
 {
     __shared__ uint32_t s_h[kMaxRadixPasses][kRadixBins];
@@ -385,7 +385,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_ghist(const uint32_t *__
         if (i < n) {
             const uint32_t k = keys[i];
             for (int p = 0; p < passes; ++p)
-                atomicAdd(&s_h[p][(k >> (kRadixBits * p)) & (kRadixBins - 1)], 1u);
+                atomicAdd(&s_h[p][(k >> (low_bit + kRadixBits * p)) & (kRadixBins - 1)], 1u);
         }
     }
     __syncthreads();
@@ -508,18 +508,19 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_pass(
 int64_t radix_tiles(int64_t n) { return n > 0 ? (n + kSortTile - 1) / kSortTile : 1; }
 
 int launch_radix_sort(const SortBuffers &b, int64_t n, int bits, hipStream_t s, const float2 *xy,
-                      Point *pts, float2 *anchor)
+                      Point *pts, float2 *anchor, int low_bit)
 {
     int cur = 0;
     if (n < 1 || (n == 1 && !pts)) return cur;
     const uint32_t ntiles = (uint32_t)radix_tiles(n);
     const int passes = (bits + kRadixBits - 1) / kRadixBits;
     const uint32_t gblocks = (uint32_t)((n + kSortThreads * kGhistItems - 1) / (kSortThreads * kGhistItems));
-    k_radix_ghist<<<gblocks, kSortThreads, 0, s>>>(b.keys[0], (uint32_t)n, passes, b.ghist);
+    k_radix_ghist<<<gblocks, kSortThreads, 0, s>>>(b.keys[0], (uint32_t)n, passes, low_bit,
+                                                   b.ghist);
     for (int p = 0; p < passes; ++p) {
         k_radix_pass<<<ntiles, kSortThreads, 0, s>>>(
             b.keys[cur], b.vals[cur], b.keys[cur ^ 1], b.vals[cur ^ 1], (uint32_t)n,
-            kRadixBits * p, b.ghist + p * kRadixBins,
+            low_bit + kRadixBits * p, b.ghist + p * kRadixBins,
             b.status + (uint64_t)p * ntiles * kRadixBins, b.tickets + p, b.err, b.epoch,
             p == passes - 1 ? xy : nullptr, p == passes - 1 ? pts : nullptr,
             p == passes - 1 ? anchor : nullptr);
@@ -1011,7 +1012,11 @@ void launch_build_index(IndexBuffers &b, const float *x, const float *y, int64_t
                                           epoch);
     k_morton<<<g, T, 0, s>>>(x, y, nn, b.sort.keys[0], b.sort.vals[0], b.xy, b.ctr, b.ws.base,
                              words, epoch);
-    const int res = launch_radix_sort(b.sort, n, 2 * kCodeLevels, s, b.xy, b.pts, b.anchor);
+    // Objects are ordered by their Morton code at level L (the top 2L bits
+    // of the level-16 code), ties by id: no leaf lies below L, so the lower
+    // bits order nothing the index or the queries depend on.
+    const int res = launch_radix_sort(b.sort, n, 2 * L, s, b.xy, b.pts, b.anchor,
+                                      2 * (kCodeLevels - L));
     const uint32_t *codes = b.sort.keys[res];
     // Binary-search steps over a window of th positions.
     int steps = 1;

@@ -123,11 +123,9 @@ int64_t radix_tiles(int64_t n);
 // scan of n values) needs.
 int64_t workspace_words(int64_t n);
 
-// Carve a sort workspace (n keys) and `scans` scan workspaces (n values
-// each) from ws; returns the number of words used.  The words must be
-// zeroed before the first pass runs.
-// Carves sort and scan workspace for n items from ws; look-back failures
-// raise *err to epoch.  Returns the words used (all must be zeroed).
+// Carve a sort workspace (n keys) and `n_scans` scan workspaces (n values
+// each) from ws; look-back failures raise *err to epoch.  Returns the
+// number of words used, which must be zeroed before the first pass runs.
 int64_t carve_workspace(const Workspace &ws, int64_t n, SortBuffers *sort, ScanSpace *scans,
                         int n_scans, uint32_t *err, uint32_t epoch);
 
@@ -140,15 +138,15 @@ void launch_zero_words(uint64_t *p, int64_t words, hipStream_t s);
 void launch_exclusive_scan(const uint32_t *in, uint32_t *out, int64_t n, const ScanSpace &sp,
                            uint32_t *total, hipStream_t s, const uint32_t *n_dev = nullptr);
 
-// Stable LSD radix sort of (key, val) pairs by key bits [0, bits) (at most
-// 32); the result ends in keys[res], vals[res] where res is returned.  The
-// workspace in b must be zero (it is consumed).
-// Sorts (keys, vals) by key; returns the buffer index holding the result.
-// With pts, the last pass writes keys and, instead of vals, the records
-// {xy[val], val, key} to pts (the index build's sorted objects).
+// Stable LSD radix sort of (key, val) pairs by key bits [low_bit, low_bit +
+// bits) (at most 32; bits above are zero or past the top of the key); the
+// result ends in keys[res], vals[res] where res is returned.  The workspace
+// in b must be zero (it is consumed).  With pts, the last pass writes keys
+// and, instead of vals, the records {xy[val], val, key} to pts (the index
+// build's sorted objects).
 int launch_radix_sort(const SortBuffers &b, int64_t n, int bits, hipStream_t s,
                       const float2 *xy = nullptr, Point *pts = nullptr,
-                      float2 *anchor = nullptr);
+                      float2 *anchor = nullptr, int low_bit = 0);
 // Refit tick: new positions into the sorted records of the last full build
 // (same objects, same order, same leaves) and the drift since that build.
 void launch_refit(IndexBuffers &b, const float *x, const float *y, int64_t n, uint32_t epoch,

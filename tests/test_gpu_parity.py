@@ -90,12 +90,12 @@ def test_uniform_10k_full_parity():
 
 def test_clustered_1m_all_ticks_full_parity():
     """The benchmark's 1M-object workload, every tick, every query, in the
-    configuration bench.py times (leaf capacity 64, one context advanced
-    tick after tick): the whole result against the oracle, and
+    configuration bench.py times (leaf capacity 64, maximum level 12, one
+    context advanced tick after tick): the whole result against the oracle, and
     2,000 sampled queries per tick against brute force."""
     w = workloads.clustered_1m()
     k = w.k
-    with binding.Context(w.n, w.n, k, leaf_capacity=64, k_hint=k) as c:
+    with binding.Context(w.n, w.n, k, leaf_capacity=64, k_hint=k, max_level=12) as c:
         for t in range(w.ticks):
             x, y, _, _, _ = w.tick(t)
             say("clustered_1m tick %d" % t)
