@@ -356,7 +356,7 @@ __global__ void k_morton(const float *__restrict__ x, const float *__restrict__ 
 //     gather follows.
 // ---------------------------------------------------------------------------
 
-constexpr int kGhistItems = 8;  // keys per thread in the histogram kernel
+constexpr int kGhistItems = 16;  // keys per thread in the histogram kernel
 
 // Lanes of the wavefront (among `valid`) holding the same 8-bit digit d.
 __device__ __forceinline__ uint64_t digit_peers(uint32_t d, uint64_t valid)
