@@ -1,8 +1,8 @@
 """Benchmark of the per-tick k-NN join on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload clustered_1m]
-                    [--leaf-capacity TH | --autotune] [--no-graph] [--counters]
-                    [--no-cpu-baseline]
+                    [--leaf-capacity TH | --autotune] [--max-level L] [--no-graph]
+                    [--counters] [--no-cpu-baseline]
     python bench.py --serving [--scenes 64] [--rate R] [--slots 4]
 
 A step is one tick of the whole hot path on device-resident inputs: the
@@ -15,7 +15,8 @@ is not part of a tick).
 The leaf capacity is the autotuner's choice for the workload on MI355X
 (TUNED_LEAF_CAPACITY), --leaf-capacity TH, or, with --autotune, chosen
 during warm-up by the autotuner (device time per tick over a few
-candidates).  Results do not depend on it.
+candidates); the maximum quadtree level is TUNED_MAX_LEVEL's or
+--max-level.  Results depend on neither.
 
 Prints one JSON line: queries/s over the K timed ticks, p50/p99 tick latency,
 a roofline entry for the dominant kernel (the leaf-sweep query kernel,

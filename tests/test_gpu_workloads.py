@@ -48,10 +48,10 @@ def rows_block(ctx, r0, r1, k):
 
 def test_network_4m_all_ticks():
     """The road-graph workload in the benchmark's configuration (leaf
-    capacity 64, maximum level 12, 4M objects, a fresh half of them querying each tick with k
-    in {8,16,32,64}): all 20 ticks on the GPU, the whole result against the
-    oracle on ticks 0, 10 and 19, and 1,000 sampled queries per tick against
-    brute force."""
+    capacity 64, maximum level 12, 4M objects, a fresh half of them querying
+    each tick with k in {8,16,32,64}): all 20 ticks on the GPU, the whole
+    result against the oracle on ticks 0, 10 and 19, and 1,000 sampled
+    queries per tick against brute force."""
     w = workloads.network_4m()
     with binding.Context(w.n, w.n // 2 + 1, 64, leaf_capacity=64, k_hint=64, max_level=12) as c:
         for t in range(w.ticks):
