@@ -49,8 +49,14 @@ def test_query_kernel_bytes():
 @pytest.mark.parametrize("workload", ["clustered_1m", "uniform_10k"])
 def test_traffic_only_for_matching_sources(workload):
     m = bench.MEASURED_TRAFFIC
-    got = bench.measured_traffic(workload, m["leaf_capacity"])
+    got = bench.measured_traffic(workload, m["leaf_capacity"], m.get("max_level", 16))
     if workload != m["workload"] or m["digest"] != bench.query_source_digest():
         assert got is None
     else:
         assert got == m["fetch_bytes"] + m["write_bytes"]
+
+
+def test_traffic_needs_the_same_maximum_level():
+    m = bench.MEASURED_TRAFFIC
+    other = 16 if m.get("max_level", 16) != 16 else 12
+    assert bench.measured_traffic(m["workload"], m["leaf_capacity"], other) is None
