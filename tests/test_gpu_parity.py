@@ -128,7 +128,7 @@ def test_families_many_k_and_th(kind):
             assert_rows_equal(got, exp, "%s k=%d th=%d" % (kind, k, th))
 
 
-@pytest.mark.parametrize("L", [1, 3, 8, 16])
+@pytest.mark.parametrize("L", [1, 3, 8, 12, 13, 16])
 def test_max_level(L):
     x, y = family("clustered", 2500, 22)
     exp = oracle.brute_knn(x, y, k=16, threads=16)
@@ -173,7 +173,8 @@ def test_ties_lattice_duplicates_and_denormals():
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("kind", ["uniform", "clustered", "duplicates", "boundary"])
-@pytest.mark.parametrize("th,L", [(1, 16), (5, 4), (64, 16), (384, 16), (5000, 16)])
+@pytest.mark.parametrize("th,L", [(1, 16), (5, 4), (2, 7), (3, 12), (8, 13), (64, 16), (384, 16),
+                                  (5000, 16)])
 def test_index_matches_oracle(kind, th, L):
     x, y = family(kind, 5000, 24)
     exp = oracle.build_index(x, y, th, L)

@@ -171,7 +171,7 @@ def _check_index(x, y, th, L):
 
 
 @pytest.mark.parametrize("kind", FAMILIES)
-@pytest.mark.parametrize("th,L", [(1, 16), (4, 4), (16, 16), (64, 1), (3000, 16)])
+@pytest.mark.parametrize("th,L", [(1, 16), (4, 4), (16, 16), (64, 1), (8, 12), (3, 13), (3000, 16)])
 def test_index_structure(kind, th, L):
     x, y = family(kind, 700, 1)
     _check_index(x, y, th, L)
