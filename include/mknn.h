@@ -173,9 +173,12 @@ MKNN_API int mknn_load_positions(mknn_ctx *ctx, const float *x, const float *y, 
 
 /*
  * mknn_advance_tick -- enqueue the index build over the current snapshot
- * (Sec. 4.1: Morton codes at level 16, radix sort of (code, id), split of
- * every quadrant holding more than the leaf capacity up to max_level, leaf
- * and node tables).  Asynchronous.  Errors: MKNN_E_STATE (nothing loaded).
+ * (Sec. 4.1: Morton codes at level 16, a stable radix sort of the objects
+ * by their code at max_level (its top 2 * max_level bits; objects of one
+ * max_level cell stay in id order), split of every quadrant holding more
+ * than the leaf capacity up to max_level, leaf and node tables).  A lower
+ * max_level sorts fewer bits (one radix pass per 8).  Asynchronous.
+ * Errors: MKNN_E_STATE (nothing loaded).
  */
 MKNN_API int mknn_advance_tick(mknn_ctx *ctx);
 
@@ -270,7 +273,8 @@ MKNN_API int mknn_result_device(const mknn_ctx *ctx, const int32_t **ids, const 
 /*
  * mknn_index_fetch -- synchronise and copy the current index to host
  * buffers, for inspection and tests.  Objects: codes[n] (level-16 Morton
- * codes in sorted order) and ids[n] (object id at each sorted position).
+ * codes in sorted order: ascending by their top 2 * max_level bits, then by
+ * id) and ids[n] (object id at each sorted position).
  * Leaves, in Morton order: level[L], prefix[L] (quadrant id at its level),
  * begin[L], end[L] (half-open range of sorted positions); leaf_cap is the
  * room in the leaf arrays, *n_leaves receives the leaf count (the call
