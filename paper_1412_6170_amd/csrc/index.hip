@@ -342,7 +342,7 @@ __global__ void k_morton(const float *__restrict__ x, const float *__restrict__ 
 //
 // k_radix_ghist counts every pass's digits over all keys in one read (keys
 // do not change between passes, only their order), in LDS per workgroup.  Each pass then runs one
-// kernel over tiles of kSortTile keys:
+// kernel over tiles of 4096 keys (8192 for large sorts):
 //   * wavefront w of the tile owns a contiguous quarter of it and ranks its
 //     keys in rounds of 64 in position order; lanes holding the same digit
 //     are found with ballots, and a wavefront-private LDS counter per digit
@@ -395,6 +395,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_ghist(const uint32_t *__
     }
 }
 
+template <int ITEMS>
 __global__ __launch_bounds__(kSortThreads) void k_radix_pass(
     const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ vals_in,
     uint32_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out, uint32_t n, int shift,
@@ -403,9 +404,10 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_pass(
     Point *__restrict__ pts, float2 *__restrict__ anchor)
 {
     constexpr int NW = kSortThreads / kWave;
-    constexpr int PER_WAVE = kWave * kSortItems;
-    __shared__ uint32_t s_keys[kSortTile];
-    __shared__ uint32_t s_vals[kSortTile];
+    constexpr int TILE = kSortThreads * ITEMS;
+    constexpr int PER_WAVE = kWave * ITEMS;
+    __shared__ uint32_t s_keys[TILE];
+    __shared__ uint32_t s_vals[TILE];
     __shared__ uint32_t s_wc[NW][kRadixBins];  // per-wavefront digit counts, then bases
     __shared__ uint32_t s_start[kRadixBins];   // start of each digit's run in the tile
     __shared__ uint32_t s_base[kRadixBins];    // destination of each digit's run
@@ -414,24 +416,24 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_pass(
 #pragma unroll
     for (int q = 0; q < NW; ++q) s_wc[q][t] = 0;
     const uint32_t tile = take_ticket(ticket);  // also orders the clearing above
-    const uint32_t base = tile * (uint32_t)kSortTile;
-    const uint32_t n_valid = min((uint32_t)kSortTile, n - base);
+    const uint32_t base = tile * (uint32_t)TILE;
+    const uint32_t n_valid = min((uint32_t)TILE, n - base);
     const uint64_t lt_mask = (1ull << lane) - 1ull;
 
     // Wavefront w owns tile positions [w * PER_WAVE, (w + 1) * PER_WAVE);
     // round j of lane l holds position w * PER_WAVE + j * 64 + l.  Padding
     // keys (all ones) take the last digit and the last positions, so they
     // rank after every real key.
-    uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
+    uint32_t key[ITEMS], val[ITEMS], rank[ITEMS];
 #pragma unroll
-    for (int j = 0; j < kSortItems; ++j) {
+    for (int j = 0; j < ITEMS; ++j) {
         const uint32_t p = w * PER_WAVE + j * kWave + lane;
         const bool v = p < n_valid;
         key[j] = v ? keys_in[base + p] : 0xffffffffu;
         val[j] = v ? vals_in[base + p] : 0u;
     }
 #pragma unroll
-    for (int j = 0; j < kSortItems; ++j) {
+    for (int j = 0; j < ITEMS; ++j) {
         const uint32_t d = (key[j] >> shift) & (kRadixBins - 1);
         const uint64_t peers = digit_peers(d, ~0ull);
         const uint32_t below = (uint32_t)__popcll(peers & lt_mask);
@@ -454,12 +456,12 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_pass(
     }
     // Publish this tile's count of digit t (padding excluded) before
     // anything else, so later tiles can resolve while this one reorders.
-    const uint32_t real = cnt - (t == kRadixBins - 1 ? (uint32_t)kSortTile - n_valid : 0u);
+    const uint32_t real = cnt - (t == kRadixBins - 1 ? (uint32_t)TILE - n_valid : 0u);
     lb_publish(status + t, kRadixBins, tile, real);
     s_start[t] = block_excl_scan<kSortThreads>(cnt, nullptr);
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < kSortItems; ++j) {
+    for (int j = 0; j < ITEMS; ++j) {
         const uint32_t d = (key[j] >> shift) & (kRadixBins - 1);
         const uint32_t local = s_start[d] + s_wc[w][d] + rank[j];
         s_keys[local] = key[j];
@@ -475,7 +477,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_pass(
     }
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < kSortItems; ++j) {
+    for (int j = 0; j < ITEMS; ++j) {
         const uint32_t lp = j * kSortThreads + t;
         if (lp < n_valid) {
             const uint32_t k = s_keys[lp];
@@ -505,7 +507,22 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_pass(
     }
 }
 
-int64_t radix_tiles(int64_t n) { return n > 0 ? (n + kSortTile - 1) / kSortTile : 1; }
+static int sort_items(int64_t n) { return n >= kSortLargeKeys ? kSortItemsLarge : kSortItems; }
+
+int64_t radix_tiles(int64_t n)
+{
+    const int64_t tile = (int64_t)kSortThreads * sort_items(n);
+    return n > 0 ? (n + tile - 1) / tile : 1;
+}
+
+// Look-back words are sized with the smaller tile, an upper bound of
+// radix_tiles(m) for every m <= n (the tile count drops where the larger
+// tiles start).
+static int64_t radix_tiles_bound(int64_t n)
+{
+    const int64_t tile = (int64_t)kSortThreads * kSortItems;
+    return n > 0 ? (n + tile - 1) / tile : 1;
+}
 
 int launch_radix_sort(const SortBuffers &b, int64_t n, int bits, hipStream_t s, const float2 *xy,
                       Point *pts, float2 *anchor, int low_bit)
@@ -517,13 +534,15 @@ int launch_radix_sort(const SortBuffers &b, int64_t n, int bits, hipStream_t s, 
     const uint32_t gblocks = (uint32_t)((n + kSortThreads * kGhistItems - 1) / (kSortThreads * kGhistItems));
     k_radix_ghist<<<gblocks, kSortThreads, 0, s>>>(b.keys[0], (uint32_t)n, passes, low_bit,
                                                    b.ghist);
+    const bool large = sort_items(n) == kSortItemsLarge;
     for (int p = 0; p < passes; ++p) {
-        k_radix_pass<<<ntiles, kSortThreads, 0, s>>>(
+        const bool last = p == passes - 1;
+        auto pass = large ? k_radix_pass<kSortItemsLarge> : k_radix_pass<kSortItems>;
+        pass<<<ntiles, kSortThreads, 0, s>>>(
             b.keys[cur], b.vals[cur], b.keys[cur ^ 1], b.vals[cur ^ 1], (uint32_t)n,
             low_bit + kRadixBits * p, b.ghist + p * kRadixBins,
             b.status + (uint64_t)p * ntiles * kRadixBins, b.tickets + p, b.err, b.epoch,
-            p == passes - 1 ? xy : nullptr, p == passes - 1 ? pts : nullptr,
-            p == passes - 1 ? anchor : nullptr);
+            last ? xy : nullptr, last ? pts : nullptr, last ? anchor : nullptr);
         cur ^= 1;
     }
     return cur;
@@ -533,7 +552,8 @@ int64_t workspace_words(int64_t n)
 {
     // ghist (u32) + tickets + err, then radix look-back words, then scans.
     const int64_t small = (kMaxRadixPasses * kRadixBins + 16 + 8) / 2 + 8;
-    return small + (int64_t)kMaxRadixPasses * radix_tiles(n) * kRadixBins + 4 * scan_tiles(n) + 16;
+    return small + (int64_t)kMaxRadixPasses * radix_tiles_bound(n) * kRadixBins +
+           4 * scan_tiles(n) + 16;
 }
 
 int64_t carve_workspace(const Workspace &ws, int64_t n, SortBuffers *sort, ScanSpace *scans,

@@ -13,8 +13,12 @@ constexpr int kWave = 64;             // CDNA wavefront width
 constexpr int kRadixBits = 8;         // LSD radix sort digit
 constexpr int kRadixBins = 1 << kRadixBits;
 constexpr int kSortThreads = 256;     // one workgroup = 4 waves
-constexpr int kSortItems = 16;        // keys per thread per tile
-constexpr int kSortTile = kSortThreads * kSortItems;
+// Keys per thread of a radix tile: 4096-key tiles, or 8192-key tiles from
+// kSortLargeKeys keys on (fewer tiles shorten the look-back chains of large
+// sorts; below it the larger tiles leave CUs idle).
+constexpr int kSortItems = 16;
+constexpr int kSortItemsLarge = 32;
+constexpr int64_t kSortLargeKeys = int64_t(1) << 21;
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kScanThreads * kScanItems;
@@ -117,7 +121,7 @@ struct IndexBuffers {
 
 // Tiles of a single-pass scan over n items.
 int64_t scan_tiles(int64_t n);
-// Radix sort tiles for n keys.
+// Radix sort tiles for n keys (tile size chosen by n).
 int64_t radix_tiles(int64_t n);
 // Workspace words a build over n objects (or a query sort of n keys plus a
 // scan of n values) needs.

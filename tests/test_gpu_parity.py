@@ -186,6 +186,30 @@ def test_index_matches_oracle(kind, th, L):
         assert same(got[key], exp[key]), key
 
 
+def test_sort_tile_size_boundary():
+    """The radix sort switches to larger tiles at 2^21 keys; one context
+    sized above the switch sorts n just below, at and above it (its
+    workspace was sized for the largest tile count any n up to its capacity
+    needs): the order equals the oracle's, sampled rows equal brute force."""
+    cap = (1 << 21) + 4097
+    rng = np.random.default_rng(31)
+    with binding.Context(cap, cap, 4, leaf_capacity=32) as c:
+        for n in ((1 << 21) - 1, 1 << 21, cap):
+            x = rng.random(n, dtype=np.float32)
+            y = rng.random(n, dtype=np.float32)
+            say("sort tile boundary: n=%d" % n)
+            c.load_positions(torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda())
+            c.advance_tick()
+            got = c.index()
+            exp = oracle.build_index(x, y, 32, 16)
+            assert same(got["codes"], exp["codes"]) and same(got["ids"], exp["ids"])
+            c.query(k=4)
+            sample = np.sort(rng.choice(n, 100, replace=False)).astype(np.int32)
+            gi, gd, gc = c.fetch_rows(sample, 4)
+            bi, bd, bc, _ = oracle.brute_knn(x, y, issuers=sample, k=4, threads=16)
+            assert same(gi, bi) and same_bits(gd, bd) and same(gc, bc)
+
+
 # ---------------------------------------------------------------------------
 # Query subsets, variable k, device inputs
 # ---------------------------------------------------------------------------
