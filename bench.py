@@ -58,8 +58,8 @@ CPU_SAMPLE_SECONDS = 10.0
 # scaled by what the same counter reads for a plain device copy of known
 # size.  Valid only for the kernel sources they were taken on (digest of the
 # query kernel's sources); otherwise the roofline's traffic is null.
-MEASURED_TRAFFIC = {"digest": "3731d24855b3e47b", "workload": "clustered_1m", "leaf_capacity": 64,
-                    "max_level": 12, "fetch_bytes": 39_829_817, "write_bytes": 290_696_816}
+MEASURED_TRAFFIC = {"digest": "c63182bbb867eb3b", "workload": "clustered_1m", "leaf_capacity": 64,
+                    "max_level": 12, "fetch_bytes": 39_784_701, "write_bytes": 290_720_512}
 
 
 def query_source_digest():
