@@ -143,9 +143,10 @@ def test_small_n_and_k_beyond_n(n):
     for k in sorted({1, 2, max(1, n - 1), n, n + 5, 32}):
         if k > binding.MKNN_K_LIMIT:
             continue
-        say("n=%d k=%d" % (n, k))
         exp = oracle.brute_knn(x, y, k=k)
-        assert_rows_equal(gpu_knn(x, y, k=k, th=4), exp, "n=%d k=%d" % (n, k))
+        for L in (16, 12):  # the default, and the benchmark's three-pass sort
+            say("n=%d k=%d L=%d" % (n, k, L))
+            assert_rows_equal(gpu_knn(x, y, k=k, th=4, L=L), exp, "n=%d k=%d L=%d" % (n, k, L))
 
 
 def test_ties_lattice_duplicates_and_denormals():
