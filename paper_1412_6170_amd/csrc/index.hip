@@ -3,10 +3,10 @@
 //   k_morton         level-16 Morton code per object (the virtual full
 //                    quadtree at l_max = 16), x cell in the even bits;
 //                    device-side range validation
-//   radix sort       stable LSD sort of (code, id), 8-bit digits, tiles
-//                    staged in LDS and written back in digit runs; the
-//                    last pass writes the sorted objects as 16-byte records
-//                    {x, y, id, code}
+//   radix sort       stable LSD sort of (level-L code, id) -- the top 2L
+//                    bits of the codes -- 8-bit digits, tiles staged in LDS
+//                    and written back in digit runs; the last pass writes
+//                    the sorted objects as 16-byte records {id, x, y, code}
 //   k_leaves         which adjacent sorted objects fall in different leaves,
 //                    scanned in the same pass into leaf ranges
 //   k_leaf_nodes     leaf level and the node count each leaf contributes,

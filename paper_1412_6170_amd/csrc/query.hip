@@ -20,8 +20,9 @@
 // The paper runs each iteration as separate kernels with a host loop and
 // re-sorts the active queries between iterations; here a wavefront carries
 // its 64 queries through all iterations without leaving the kernel, so no
-// active-query sort or host round trip is needed and every candidate leaf is
-// read with wave-uniform (scalar) loads.
+// active-query sort or host round trip is needed; a candidate leaf is read
+// once per wavefront, 64 records at a time with coalesced 16-byte loads into
+// LDS, from where every lane reads each record.
 //
 // Exactness.  d2 = fl(fl(dx*dx) + fl(dy*dy)) with no contraction (this file
 // is built with -ffp-contract=off and the pragma below).  A box is skipped

@@ -60,3 +60,16 @@ def test_traffic_needs_the_same_maximum_level():
     m = bench.MEASURED_TRAFFIC
     other = 16 if m.get("max_level", 16) != 16 else 12
     assert bench.measured_traffic(m["workload"], m["leaf_capacity"], other) is None
+
+
+def test_digest_ignores_comments_not_code():
+    here = {f: open(os.path.join(ROOT, "paper_1412_6170_amd", "csrc", f)).read()
+            for f in ("query.hip", "query.hpp", "mknn_internal.hpp")}
+    base = bench.query_source_digest(here.get)
+    commented = dict(here)
+    commented["query.hip"] = "// a new comment\n/* and a block\n comment */\n" + here["query.hip"]
+    assert bench.query_source_digest(commented.get) == base
+    changed = dict(here)
+    changed["query.hpp"] = here["query.hpp"].replace("kQueryClasses = 5", "kQueryClasses = 6")
+    assert changed["query.hpp"] != here["query.hpp"]
+    assert bench.query_source_digest(changed.get) != base
