@@ -44,6 +44,7 @@
 #ifndef MKNN_H
 #define MKNN_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus

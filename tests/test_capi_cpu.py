@@ -94,3 +94,25 @@ def test_footprint_at_the_largest_sizes():
         binding.footprint(n_max=2 ** 31, k_max=8)
     with pytest.raises(binding.MknnError):
         binding.footprint(n_max=1000, k_max=129)
+
+
+def test_readme_c_example_compiles(tmp_path):
+    """The C usage example in README.md compiles against include/mknn.h."""
+    import re
+    import shutil
+    import subprocess
+    if not shutil.which("gcc"):
+        pytest.skip("gcc not available")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    text = open(os.path.join(root, "README.md")).read()
+    block = re.search(r"```c\n(.*?)```", text, re.S).group(1)
+    include = "\n".join(l for l in block.splitlines() if l.startswith("#include"))
+    body = "\n".join(l for l in block.splitlines() if not l.startswith("#include"))
+    src = tmp_path / "example.c"
+    src.write_text(include + "\n#include <stdint.h>\n"
+                   "void example(int64_t n, int ticks, float **x, float **y, int32_t *ids,\n"
+                   "             float *d2, int32_t *counts)\n{\n" + body + "\n}\n")
+    r = subprocess.run(["gcc", "-std=c11", "-fsyntax-only", "-Wall", "-Werror",
+                        "-I", os.path.join(root, "include"), str(src)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
