@@ -35,13 +35,14 @@ def check(got, exp):
     assert np.array_equal(got[0], exp[0]) and same_bits(got[1], exp[1])
 
 
-def test_refit_ticks_moving_clusters():
+@pytest.mark.parametrize("L", [16, 12])
+def test_refit_ticks_moving_clusters(L):
     w = workloads.clustered_1m(n=200_000, ticks=6)
     k = 32
-    with binding.Context(w.n, w.n, k, leaf_capacity=32) as c:
+    with binding.Context(w.n, w.n, k, leaf_capacity=32, max_level=L) as c:
         for t in range(w.ticks):
             x, y, _, _, _ = w.tick(t)
-            say("refit clustered_200k tick %d" % t)
+            say("refit clustered_200k L=%d tick %d" % (L, t))
             c.load_positions(torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda())
             if t == 0:
                 c.advance_tick()
