@@ -306,6 +306,21 @@ MKNN_API int mknn_set_leaf_capacity(mknn_ctx *ctx, int32_t th);
  * (the means and totals in mknn_stats restart). */
 MKNN_API int mknn_reset_timing(mknn_ctx *ctx);
 
+/*
+ * mknn_query_time -- device time in ms (all kernels) of an earlier query:
+ * back = 0 is the last query enqueued, 1 the one before, and so on (up to
+ * 255).  With wait = 0 it never blocks; with wait != 0 it waits for that
+ * query only (not for later work on the stream).  For decisions taken while
+ * later ticks are still running, such as when to rebuild the index (Sec.
+ * 4.1): waiting for the query two ticks back keeps the host at most two
+ * ticks ahead without ever leaving the GPU idle, unlike mknn_get_stats,
+ * which synchronises the stream.  Needs MKNN_FLAG_TIMING.
+ * Errors: MKNN_E_INVAL (NULL, back out of range, no such query yet),
+ * MKNN_E_STATE (wait = 0 and that query has not finished, or it was not
+ * timed; *ms is left unchanged).
+ */
+MKNN_API int mknn_query_time(const mknn_ctx *ctx, int32_t back, int32_t wait, float *ms);
+
 /* mknn_last_error -- message of the context's last error ("" if none). */
 MKNN_API const char *mknn_last_error(const mknn_ctx *ctx);
 

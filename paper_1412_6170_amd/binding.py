@@ -82,6 +82,7 @@ def lib():
                                   ctypes.POINTER(_i64)], _i32),
             "mknn_sync": ([_vp], _i32),
             "mknn_reset_timing": ([_vp], _i32),
+            "mknn_query_time": ([_vp, _i32, _i32, ctypes.POINTER(ctypes.c_float)], _i32),
             "mknn_set_leaf_capacity": ([_vp, _i32], _i32),
             "mknn_get_stats": ([_vp, ctypes.POINTER(Stats)], _i32),
             "mknn_last_error": ([_vp], ctypes.c_char_p),
@@ -316,6 +317,17 @@ class Context:
     def reset_timing(self):
         self._check(lib().mknn_reset_timing(self._h))
 
+    def query_time(self, back=0, wait=False):
+        """Device ms of an earlier query (back = 0: the last one enqueued).
+        With wait, blocks until that query (only) has finished; without,
+        returns None if it has not."""
+        ms = ctypes.c_float()
+        rc = lib().mknn_query_time(self._h, int(back), 1 if wait else 0, ctypes.byref(ms))
+        if rc == -3:  # MKNN_E_STATE: still running
+            return None
+        self._check(rc)
+        return ms.value
+
     def set_leaf_capacity(self, th):
         self._check(lib().mknn_set_leaf_capacity(self._h, int(th)))
 
@@ -352,43 +364,53 @@ class Context:
 
 class ReusePolicy:
     """When to rebuild the index (Sec. 4.1: rebuild only when the work of the
-    last tick exceeds that of recent ticks by some factor).  After a full
-    build the first query's device time is the reference; later ticks refit
-    the index while the last query stays within ``factor`` times that
-    reference (and at most ``max_refits`` ticks in a row), otherwise they
-    rebuild.  Needs a context created with timing=True; ``tick`` reads the
-    previous query's time (waiting for it to finish) before it loads the new
-    positions, since a load starts a new tick."""
+    last tick exceeds that of recent ticks by some factor).  The query of a
+    tick with a full build is the reference; later ticks refit the index
+    while queries stay within ``factor`` times that reference (and at most
+    ``max_refits`` ticks in a row), otherwise they rebuild.  The decision
+    reads the time of the query two ticks back, waiting for that query only:
+    the host stays at most two ticks ahead while the last tick keeps the GPU
+    busy (waiting for the last query instead would leave the GPU idle while
+    the next tick is enqueued).  Queries older than the last full build are
+    ignored.  Needs a context created with timing=True."""
 
-    def __init__(self, factor=1.3, max_refits=None):
+    def __init__(self, factor=1.15, max_refits=None):
         self.factor = float(factor)
         self.max_refits = max_refits
         self.reference = None
         self.rebuilds = 0
         self.refits = 0
-        self._after_build = False
+        self._ticks = 0         # ticks enqueued
+        self._last_build = -1   # tick of the last full build
+        self._streak = 0        # refit ticks in a row
+        self._last = None       # latest query time seen since that build
 
     def tick(self, ctx, x, y):
         """Load the tick's positions and enqueue its index step."""
-        last = None
-        if ctx.stats_ready():
-            st = ctx.stats()
-            last = st["ms_query"] if st["nq"] else None
-            if self._after_build and last:
-                self.reference = last
-        self._after_build = False
-        refits = ctx.stats()["refits"] if last is not None else 0
-        refit = (self.reference is not None and last is not None
-                 and last <= self.factor * self.reference
-                 and (self.max_refits is None or refits < self.max_refits))
+        q = self._ticks - 2     # the query read below: two ticks back
+        if q >= 0 and q >= self._last_build:
+            t = ctx.query_time(back=1, wait=True)
+            if t is not None:
+                if q == self._last_build:
+                    self.reference = t
+                else:
+                    self._last = t
+        refit = (self._ticks > 0
+                 and (self.reference is None or self._last is None
+                      or self._last <= self.factor * self.reference)
+                 and (self.max_refits is None or self._streak < self.max_refits))
         ctx.load_positions(x, y)
         if refit:
             ctx.refit_tick()
             self.refits += 1
+            self._streak += 1
         else:
             ctx.advance_tick()
             self.rebuilds += 1
-            self._after_build = True
+            self._streak = 0
+            self._last_build = self._ticks
+            self._last = None
+        self._ticks += 1
         return "refit" if refit else "build"
 
 

@@ -912,6 +912,29 @@ int mknn_reset_timing(mknn_ctx *c)
     return check_launch(c, "reset counters");
 }
 
+int mknn_query_time(const mknn_ctx *cc, int32_t back, int32_t wait, float *ms)
+{
+    mknn_ctx *c = const_cast<mknn_ctx *>(cc);
+    if (!c || !ms) return MKNN_E_INVAL;
+    if (!((c->cfg.flags & MKNN_FLAG_TIMING) && c->have_ring))
+        return fail(c, MKNN_E_INVAL, "query_time needs MKNN_FLAG_TIMING%s");
+    if (back < 0 || back >= mknn_ctx::kRing || (int64_t)back >= c->query_slot)
+        return fail(c, MKNN_E_INVAL, "no such query%s");
+    const int64_t slot = (c->query_slot - 1 - back) % mknn_ctx::kRing;
+    // Not finished (or never timed): report it without leaving a HIP error
+    // behind for the next launch check to find.
+    hipEvent_t end = c->ring[slot][4];
+    float t = 0;
+    if (wait) (void)hipEventSynchronize(end);
+    if (hipEventQuery(end) != hipSuccess ||
+        hipEventElapsedTime(&t, c->ring[slot][2], end) != hipSuccess) {
+        (void)hipGetLastError();
+        return MKNN_E_STATE;
+    }
+    *ms = t;
+    return MKNN_OK;
+}
+
 int mknn_get_stats(const mknn_ctx *cc, mknn_stats *out)
 {
     mknn_ctx *c = const_cast<mknn_ctx *>(cc);

@@ -54,6 +54,8 @@ def test_null_arguments_are_rejected_without_a_device():
     assert lib.mknn_destroy(None) == 0
     assert lib.mknn_advance_tick(None) == -1
     assert lib.mknn_sync(None) == -1
+    ms = ctypes.c_float()
+    assert lib.mknn_query_time(None, 0, 0, ctypes.byref(ms)) == -1
     assert lib.mknn_last_error(None).decode() == "null context"
     cfg = binding.Config()
     cfg.n_max, cfg.q_max, cfg.k_max = 10, 10, 0      # k_max out of range

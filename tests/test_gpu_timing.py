@@ -82,3 +82,23 @@ def test_timing_off_reports_zero():
         c.sync()
         st = c.stats()
         assert st["ms_build"] == 0 and st["ms_query_main"] == 0 and st["timed_ticks"] == 0
+
+
+def test_query_time_without_waiting():
+    w = workloads.uniform_10k()
+    x, y, _, _, k = w.tick(0)
+    with binding.Context(len(x), len(x), k, timing=True) as c:
+        for _ in range(3):
+            run(c, x, y, k)
+        c.sync()
+        st = c.stats()
+        last = c.query_time(0)
+        assert last == st["ms_query"] and last > 0
+        assert c.query_time(1) > 0 and c.query_time(2) > 0
+        with pytest.raises(binding.MknnError):
+            c.query_time(3)      # only three queries so far
+    with binding.Context(len(x), len(x), k) as c:
+        run(c, x, y, k)
+        c.sync()
+        with pytest.raises(binding.MknnError):
+            c.query_time(0)      # timing off
