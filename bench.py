@@ -60,7 +60,7 @@ CPU_SAMPLE_SECONDS = 10.0
 # query kernel's sources without comments); otherwise the roofline's traffic
 # is null.
 MEASURED_TRAFFIC = {"digest": "3ad1811ceb98fa0f", "workload": "clustered_1m", "leaf_capacity": 64,
-                    "max_level": 12, "fetch_bytes": 39_784_701, "write_bytes": 290_720_512}
+                    "max_level": 12, "fetch_bytes": 39_750_720, "write_bytes": 290_701_080}
 
 
 def code_only(text):
