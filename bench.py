@@ -56,11 +56,12 @@ CPU_SAMPLE_SECONDS = 10.0
 # HBM bytes per launch of the query kernel on clustered_1m at the tuned leaf
 # capacity, from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE), each
 # scaled by what the same counter reads for a plain device copy of known
-# size.  Valid only for the kernel code they were taken on (digest of the
+# size, and its VALU instructions per launch (SQ_INSTS_VALU, a third run).  Valid only for the kernel code they were taken on (digest of the
 # query kernel's sources without comments); otherwise the roofline's traffic
 # is null.
 MEASURED_TRAFFIC = {"digest": "3ad1811ceb98fa0f", "workload": "clustered_1m", "leaf_capacity": 64,
-                    "max_level": 12, "fetch_bytes": 39_750_720, "write_bytes": 290_701_080}
+                    "max_level": 12, "fetch_bytes": 39_750_720, "write_bytes": 290_701_080,
+                    "valu_insts": 190_235_337}
 
 
 def code_only(text):
@@ -85,12 +86,37 @@ def query_source_digest(read=None):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, leaf_capacity, max_level=16):
+def _measured(workload, leaf_capacity, max_level):
     m = MEASURED_TRAFFIC
     if (not m or m["digest"] != query_source_digest() or m["workload"] != workload
             or m["leaf_capacity"] != leaf_capacity or m.get("max_level", 16) != max_level):
         return None
-    return m["fetch_bytes"] + m["write_bytes"]
+    return m
+
+
+def measured_traffic(workload, leaf_capacity, max_level=16):
+    m = _measured(workload, leaf_capacity, max_level)
+    return None if m is None else m["fetch_bytes"] + m["write_bytes"]
+
+
+# VALU issue peak of MI355X without packed arithmetic: 256 CUs x 4 SIMDs x
+# 16 lanes x 2.4 GHz lane operations per second.
+VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+
+
+def valu_issue(workload, leaf_capacity, max_level, kernel_ms):
+    """VALU lane operations the query kernel issues per second (the stored
+    SQ_INSTS_VALU count of one launch, 64 lanes each, over the kernel's
+    measured mean time) against the issue peak, or None if the count was
+    taken on other code or another configuration."""
+    m = _measured(workload, leaf_capacity, max_level)
+    if m is None or not m.get("valu_insts") or not kernel_ms:
+        return None
+    ops = m["valu_insts"] * 64 / (kernel_ms * 1e-3)
+    return {"bound": "alu", "achieved": ops / 1e12, "peak": VALU_PEAK_LANE_OPS / 1e12,
+            "unit": "T lane-ops/s", "frac": ops / VALU_PEAK_LANE_OPS,
+            "note": "executed VALU instructions (SQ_INSTS_VALU, rocprofv3 --pmc) x 64 lanes "
+                    "per launch over the kernel's mean time; not algorithmic work"}
 
 
 def query_kernel_bytes(n, nq, entries):
@@ -450,6 +476,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(w.name, st["leaf_capacity"], max_level),
                      "kernel_ms": kern_ms, "bytes_per_launch": kern_bytes},
+        "valu_issue": valu_issue(w.name, st["leaf_capacity"], max_level, kern_ms),
         "graph": None,
         "cpu_baseline": None,
     }

@@ -73,3 +73,15 @@ def test_digest_ignores_comments_not_code():
     changed["query.hpp"] = here["query.hpp"].replace("kQueryClasses = 5", "kQueryClasses = 6")
     assert changed["query.hpp"] != here["query.hpp"]
     assert bench.query_source_digest(changed.get) != base
+
+
+def test_valu_issue_fraction():
+    m = bench.MEASURED_TRAFFIC
+    ms = 0.5
+    got = bench.valu_issue(m["workload"], m["leaf_capacity"], m.get("max_level", 16), ms)
+    if m["digest"] != bench.query_source_digest():
+        assert got is None
+        return
+    assert got["bound"] == "alu"
+    assert abs(got["frac"] - m["valu_insts"] * 64 / (ms * 1e-3) / (256 * 4 * 16 * 2.4e9)) < 1e-12
+    assert bench.valu_issue("uniform_10k", m["leaf_capacity"], 16, ms) is None
