@@ -36,7 +36,9 @@
  * Conventions: every call returns MKNN_OK (0) or a negative MKNN_E_* code;
  * mknn_last_error gives the message.  No C++ exception crosses this
  * interface.  A context is not thread-safe; separate contexts are
- * independent.  Pointers marked "device" are HIP device (or managed)
+ * independent.  A call that uses the GPU makes the context's device current
+ * while it runs and restores the calling thread's current device before it
+ * returns.  Pointers marked "device" are HIP device (or managed)
  * pointers on the context's device; "host" pointers are ordinary host
  * memory.  Work is enqueued on the context's stream and the calls return
  * before the GPU finishes, except where a call says it synchronises.

@@ -91,6 +91,30 @@ int hip_fail(mknn_ctx *c, hipError_t e, const char *where)
         if (e_ != hipSuccess) return hip_fail((ctx), e_, #call); \
     } while (0)
 
+// Makes a context's device current for one call and gives the caller its
+// own current device back when the call returns, on every path.
+class DeviceScope {
+  public:
+    explicit DeviceScope(int dev)
+    {
+        int cur = -1;
+        if (hipGetDevice(&cur) != hipSuccess) cur = -1;
+        if (cur == dev) return;  // already current: nothing to restore
+        err = hipSetDevice(dev);
+        if (err == hipSuccess) prev_ = cur;
+    }
+    ~DeviceScope()
+    {
+        if (prev_ >= 0) (void)hipSetDevice(prev_);
+    }
+    DeviceScope(const DeviceScope &) = delete;
+    DeviceScope &operator=(const DeviceScope &) = delete;
+    hipError_t err = hipSuccess;
+
+  private:
+    int prev_ = -1;
+};
+
 template <typename T>
 int dalloc(mknn_ctx *c, T **p, int64_t count)
 {
@@ -306,16 +330,15 @@ const char *mknn_last_error(const mknn_ctx *c) { return c ? c->err.c_str() : "nu
 int mknn_destroy(mknn_ctx *c)
 {
     if (!c) return MKNN_OK;
-    int dev = 0;
-    (void)hipGetDevice(&dev);
-    (void)hipSetDevice(c->cfg.device);
-    if (c->stream) (void)hipStreamSynchronize(c->stream);
-    for (void *p : c->allocs) (void)hipFree(p);
-    for (auto &slot : c->ring)
-        for (auto &e : slot)
-            if (e) (void)hipEventDestroy(e);
-    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
-    (void)hipSetDevice(dev);
+    {
+        DeviceScope dev(c->cfg.device);
+        if (c->stream) (void)hipStreamSynchronize(c->stream);
+        for (void *p : c->allocs) (void)hipFree(p);
+        for (auto &slot : c->ring)
+            for (auto &e : slot)
+                if (e) (void)hipEventDestroy(e);
+        if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    }
     delete c;
     return MKNN_OK;
 }
@@ -348,8 +371,8 @@ int mknn_create(const mknn_config *cfg, mknn_ctx **out)
     if (!c) return MKNN_E_NOMEM;
     configure(c, cfg);
 
-    hipError_t e = hipSetDevice(cfg->device);
-    if (e != hipSuccess) {
+    DeviceScope dev(cfg->device);
+    if (dev.err != hipSuccess) {
         delete c;
         return MKNN_E_DEVICE;
     }
@@ -357,7 +380,7 @@ int mknn_create(const mknn_config *cfg, mknn_ctx **out)
     if (cfg->stream) {
         c->stream = (hipStream_t)cfg->stream;
     } else {
-        e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+        const hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
         if (e != hipSuccess) {
             delete c;
             return MKNN_E_DEVICE;
@@ -404,7 +427,8 @@ int mknn_load_positions(mknn_ctx *c, const float *x, const float *y, int64_t n, 
                             std::to_string(i).c_str());
         }
     }
-    HIP_OR_FAIL(c, hipSetDevice(c->cfg.device));
+    DeviceScope dev(c->cfg.device);
+    HIP_OR_FAIL(c, dev.err);
     if (where == MKNN_HOST) {
         if (n > 0) {
             HIP_OR_FAIL(c, hipMemcpyAsync(c->x, x, (size_t)n * sizeof(float),
@@ -433,7 +457,8 @@ int mknn_advance_tick(mknn_ctx *c)
     if (!c) return MKNN_E_INVAL;
     if (c->dead) return fail(c, MKNN_E_DEVICE, "context has a sticky device error%s");
     if (!c->loaded) return fail(c, MKNN_E_STATE, "advance_tick before load_positions%s");
-    HIP_OR_FAIL(c, hipSetDevice(c->cfg.device));
+    DeviceScope dev(c->cfg.device);
+    HIP_OR_FAIL(c, dev.err);
     int rc = mark(c, 0);
     if (rc) return rc;
     c->build_epoch = next_epoch(c->build_epoch);
@@ -461,7 +486,8 @@ int mknn_refit_tick(mknn_ctx *c)
     if (!c->built) return fail(c, MKNN_E_STATE, "refit_tick needs a full build first%s");
     if (c->n != c->built_n)
         return fail(c, MKNN_E_STATE, "refit_tick needs the object count of the last build%s");
-    HIP_OR_FAIL(c, hipSetDevice(c->cfg.device));
+    DeviceScope dev(c->cfg.device);
+    HIP_OR_FAIL(c, dev.err);
     int rc = mark(c, 0);
     if (rc) return rc;
     c->build_epoch = next_epoch(c->build_epoch);
@@ -572,7 +598,8 @@ int mknn_query_points(mknn_ctx *c, const float *qx, const float *qy, const int32
             if (rc) return rc;
         }
     }
-    HIP_OR_FAIL(c, hipSetDevice(c->cfg.device));
+    DeviceScope dev(c->cfg.device);
+    HIP_OR_FAIL(c, dev.err);
     int rc = mark(c, 2);
     if (rc) return rc;
     c->query_epoch = next_epoch(c->query_epoch);
@@ -681,7 +708,8 @@ int mknn_query(mknn_ctx *c, const int32_t *issuers, const int32_t *ks, int64_t n
             present = seen;
         }
     }
-    HIP_OR_FAIL(c, hipSetDevice(c->cfg.device));
+    DeviceScope dev(c->cfg.device);
+    HIP_OR_FAIL(c, dev.err);
     int rc = mark(c, 2);
     if (rc) return rc;
 
@@ -789,7 +817,8 @@ int mknn_sync(mknn_ctx *c)
 {
     if (!c) return MKNN_E_INVAL;
     if (c->dead) return fail(c, MKNN_E_DEVICE, "context has a sticky device error%s");
-    HIP_OR_FAIL(c, hipSetDevice(c->cfg.device));
+    DeviceScope dev(c->cfg.device);
+    HIP_OR_FAIL(c, dev.err);
     HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
     return check_deferred(c);
 }
@@ -799,6 +828,8 @@ int mknn_result_size(const mknn_ctx *cc, int64_t *nq, int64_t *entries)
     mknn_ctx *c = const_cast<mknn_ctx *>(cc);
     if (!c) return MKNN_E_INVAL;
     if (!c->queried) return fail(c, MKNN_E_STATE, "no query yet%s");
+    DeviceScope dev(c->cfg.device);
+    HIP_OR_FAIL(c, dev.err);
     int rc = resolve_entries(c);
     if (rc) return rc;
     if (nq) *nq = c->nq;
@@ -825,6 +856,8 @@ int mknn_fetch(mknn_ctx *c, int32_t *ids, float *d2, int32_t *counts, int64_t *o
     if (!c) return MKNN_E_INVAL;
     if (!valid_where(where)) return fail(c, MKNN_E_INVAL, "bad `where`%s");
     if (!c->queried) return fail(c, MKNN_E_STATE, "fetch before query%s");
+    DeviceScope dev(c->cfg.device);
+    HIP_OR_FAIL(c, dev.err);
     int rc = mknn_sync(c);
     if (rc) return rc;
     rc = resolve_entries(c);
@@ -856,6 +889,8 @@ int mknn_index_fetch(mknn_ctx *c, uint32_t *codes, int32_t *ids, int32_t *level,
 {
     if (!c) return MKNN_E_INVAL;
     if (!c->ticked) return fail(c, MKNN_E_STATE, "no index yet%s");
+    DeviceScope dev(c->cfg.device);
+    HIP_OR_FAIL(c, dev.err);
     int rc = mknn_sync(c);
     if (rc) return rc;
     IndexCounters h{};
@@ -904,6 +939,8 @@ int mknn_set_leaf_capacity(mknn_ctx *c, int32_t th)
 int mknn_reset_timing(mknn_ctx *c)
 {
     if (!c) return MKNN_E_INVAL;
+    DeviceScope dev(c->cfg.device);
+    HIP_OR_FAIL(c, dev.err);
     int rc = mknn_sync(c);
     if (rc) return rc;
     c->builds_timed = 0;
@@ -921,6 +958,8 @@ int mknn_query_time(const mknn_ctx *cc, int32_t back, int32_t wait, float *ms)
     if (back < 0 || back >= mknn_ctx::kRing || (int64_t)back >= c->query_slot)
         return fail(c, MKNN_E_INVAL, "no such query%s");
     const int64_t slot = (c->query_slot - 1 - back) % mknn_ctx::kRing;
+    DeviceScope dev(c->cfg.device);
+    if (dev.err != hipSuccess) return hip_fail(c, dev.err, "hipSetDevice");
     // Not finished (or never timed): report it without leaving a HIP error
     // behind for the next launch check to find.
     hipEvent_t end = c->ring[slot][4];
@@ -945,6 +984,8 @@ int mknn_get_stats(const mknn_ctx *cc, mknn_stats *out)
     out->nq = c->queried ? c->nq : 0;
     out->leaf_capacity = c->th;
     if (c->ticked && !c->dead) {
+        DeviceScope dev(c->cfg.device);
+        HIP_OR_FAIL(c, dev.err);
         IndexCounters h{};
         int rc = read_counters(c, &h);
         if (rc) return rc;
