@@ -102,13 +102,26 @@ _hiplib = None
 
 
 def _hip():
-    """The HIP runtime, for plain device-to-host copies of result rows."""
+    """The HIP runtime: plain device-to-host copies of result rows, and the
+    event that orders a context's stream after its inputs' producer."""
     global _hiplib
     if _hiplib is None:
-        _hiplib = ctypes.CDLL("libamdhip64.so")
-        _hiplib.hipMemcpy.argtypes = [_vp, _vp, ctypes.c_size_t, ctypes.c_int]
-        _hiplib.hipMemcpy.restype = ctypes.c_int
+        h = ctypes.CDLL("libamdhip64.so")
+        for name, args in (("hipMemcpy", [_vp, _vp, ctypes.c_size_t, ctypes.c_int]),
+                           ("hipEventCreateWithFlags", [ctypes.POINTER(_vp), ctypes.c_uint]),
+                           ("hipEventRecord", [_vp, _vp]),
+                           ("hipStreamWaitEvent", [_vp, _vp, ctypes.c_uint]),
+                           ("hipEventDestroy", [_vp])):
+            f = getattr(h, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int
+        _hiplib = h
     return _hiplib
+
+
+# hipEventDisableTiming | hipEventDisableSystemFence: an ordering-only event
+# between two streams of one device needs no system-scope release.
+_ORDER_EVENT_FLAGS = 0x2 | 0x20000000
 
 
 def default_leaf_capacity(k):
@@ -150,19 +163,83 @@ def _host_ptr(a, dtype):
 
 class Context:
     """One mknn context: device memory for n_max objects and q_max queries
-    of up to k_max neighbours each."""
+    of up to k_max neighbours each.
+
+    Work runs on the context's stream: `stream` (a torch stream or a raw
+    stream handle), else (None or the null stream) a torch stream of its
+    own.  Device inputs may still be being produced on the caller's current
+    torch stream: each call that takes them first makes the context's
+    stream wait for the work enqueued there so far, and marks them used on
+    the context's stream, so that torch's caching allocator does not hand
+    their memory out again before the context's stream has passed the
+    call."""
 
     def __init__(self, n_max, q_max=None, k_max=32, leaf_capacity=0, max_level=0, k_hint=0,
                  device=0, stream=None, timing=False, counters=False, group_k=False):
-        cfg = make_config(n_max, q_max, k_max, leaf_capacity, max_level, k_hint, device, stream,
-                          timing, counters, group_k)
+        self._h = None
+        self._order_ev = None
+        import torch
+        if isinstance(stream, torch.cuda.Stream):
+            ts = stream
+        elif stream:
+            ptr = int(stream)
+            known = (torch.cuda.current_stream(device), torch.cuda.default_stream(device))
+            ts = next((t for t in known if t.cuda_stream == ptr), None)
+            if ts is None:
+                ts = torch.cuda.ExternalStream(ptr, device=device)
+        else:
+            ts = None
+        if ts is None or not ts.cuda_stream:
+            # A null handle would ask the library for a stream of its own;
+            # take a torch stream instead, so that it has a torch object.
+            ts = torch.cuda.Stream(device=device)   # default priority
+        self._tstream = ts
+        cfg = make_config(n_max, q_max, k_max, leaf_capacity, max_level, k_hint, device,
+                          ts.cuda_stream, timing, counters, group_k)
         self.cfg = cfg
         h = _vp()
         rc = lib().mknn_create(ctypes.byref(cfg), ctypes.byref(h))
         if rc != 0:
             raise MknnError(rc, "mknn_create failed")
         self._h = h
+        ev = _vp()
+        rc = _hip().hipEventCreateWithFlags(ctypes.byref(ev), _ORDER_EVENT_FLAGS)
+        if rc != 0:
+            self.close()
+            raise MknnError(-6, "hipEventCreateWithFlags failed (%d)" % rc)
+        self._order_ev = ev
         self._keep = []
+
+    @property
+    def stream(self):
+        """The torch stream the context's work runs on."""
+        return self._tstream
+
+    def _device_inputs(self, *arrays):
+        """Order the context's stream after the caller's current stream and
+        mark device inputs as used on the context's stream (see the class
+        docstring).  Host arrays need neither: they are read during the
+        call."""
+        dev = [a for a in arrays if a is not None and _is_tensor(a) and a.is_cuda]
+        if not dev:
+            return
+        import torch
+        for a in dev:
+            if a.device.index != self.cfg.device:
+                raise ValueError("device arrays must be on the context's device (%d)"
+                                 % self.cfg.device)
+        cur = torch.cuda.current_stream(self.cfg.device)
+        if cur.cuda_stream != self._tstream.cuda_stream:
+            hip = _hip()
+            rc = hip.hipEventRecord(self._order_ev, ctypes.c_void_p(cur.cuda_stream))
+            if rc == 0:
+                rc = hip.hipStreamWaitEvent(ctypes.c_void_p(self._tstream.cuda_stream),
+                                            self._order_ev, 0)
+            if rc != 0:
+                raise MknnError(-6, "ordering the context's stream after the current "
+                                    "stream failed (%d)" % rc)
+        for a in dev:
+            a.record_stream(self._tstream)
 
     # -- plumbing ------------------------------------------------------------
     def _check(self, rc):
@@ -173,6 +250,9 @@ class Context:
         if getattr(self, "_h", None):
             lib().mknn_destroy(self._h)
             self._h = None
+        if getattr(self, "_order_ev", None):
+            _hip().hipEventDestroy(self._order_ev)
+            self._order_ev = None
 
     def __enter__(self):
         return self
@@ -206,6 +286,7 @@ class Context:
 
     # -- the four verbs ------------------------------------------------------
     def load_positions(self, x, y):
+        self._device_inputs(x, y)
         px, wx, kx = self._arg(x, np.float32)
         py, wy, ky = self._arg(y, np.float32)
         if wx != wy:
@@ -226,6 +307,7 @@ class Context:
         self._check(lib().mknn_refit_tick(self._h))
 
     def query(self, k=None, issuers=None, ks=None, nq=None):
+        self._device_inputs(issuers, ks)
         pi, wi, ki = self._arg(issuers, np.int32)
         pk, wk, kk = self._arg(ks, np.int32)
         where = wi if wi is not None else (wk if wk is not None else MKNN_HOST)
@@ -247,6 +329,7 @@ class Context:
         """Queries with free centres (qx[i], qy[i]) in [0,1)^2; object
         exclude[i] (None or -1: none) is left out.  Arrays are numpy (host)
         or torch CUDA tensors (device), all in the same place."""
+        self._device_inputs(qx, qy, exclude, ks)
         px, wx, kx = self._arg(qx, np.float32)
         py, wy, ky = self._arg(qy, np.float32)
         pe, we, ke = self._arg(exclude, np.int32)
