@@ -389,6 +389,10 @@ class Context:
         return ids, d2, cnt
 
     def result_device_ptrs(self):
+        """Device addresses of the result rows (ids, d2, counts, offsets or
+        None).  The rows are complete once the context's stream has passed
+        the query: work on another stream that reads them waits for it
+        first, e.g. torch.cuda.current_stream().wait_stream(ctx.stream)."""
         ids, d2, cnt, off = _vp(), _vp(), _vp(), _vp()
         self._check(lib().mknn_result_device(self._h, ctypes.byref(ids), ctypes.byref(d2),
                                              ctypes.byref(cnt), ctypes.byref(off)))
