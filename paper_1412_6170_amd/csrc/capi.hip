@@ -600,10 +600,6 @@ int mknn_query_points(mknn_ctx *c, const float *qx, const float *qy, const int32
     }
     DeviceScope dev(c->cfg.device);
     HIP_OR_FAIL(c, dev.err);
-    int rc = mark(c, 2);
-    if (rc) return rc;
-    c->query_epoch = next_epoch(c->query_epoch);
-
     const float *d_qx = qx, *d_qy = qy;
     const int32_t *d_ex = exclude, *d_ks = ks;
     if (where == MKNN_HOST && nq > 0) {
@@ -623,7 +619,13 @@ int mknn_query_points(mknn_ctx *c, const float *qx, const float *qy, const int32
                                           c->stream));
             d_ks = c->ks;
         }
+        // Host arrays are read before the call returns: the caller may
+        // reuse them at once.
+        HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
     }
+    int rc = mark(c, 2);
+    if (rc) return rc;
+    c->query_epoch = next_epoch(c->query_epoch);
 
     QueryArgs qa = base_query_args(c, nq, ks, k_uniform);
     if (nq > 0) {
@@ -710,10 +712,6 @@ int mknn_query(mknn_ctx *c, const int32_t *issuers, const int32_t *ks, int64_t n
     }
     DeviceScope dev(c->cfg.device);
     HIP_OR_FAIL(c, dev.err);
-    int rc = mark(c, 2);
-    if (rc) return rc;
-
-    c->query_epoch = next_epoch(c->query_epoch);
     const int32_t *d_iss = issuers, *d_ks = ks;
     if (where == MKNN_HOST && nq > 0) {
         if (issuers) {
@@ -726,7 +724,13 @@ int mknn_query(mknn_ctx *c, const int32_t *issuers, const int32_t *ks, int64_t n
                                           c->stream));
             d_ks = c->ks;
         }
+        // Host arrays are read before the call returns: the caller may
+        // reuse them at once.
+        if (issuers || ks) HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
     }
+    int rc = mark(c, 2);
+    if (rc) return rc;
+    c->query_epoch = next_epoch(c->query_epoch);
 
     QueryArgs qa = base_query_args(c, nq, ks, k_uniform);
 

@@ -99,3 +99,38 @@ def test_stream_handles():
         b = c.fetch()
     for u, v in zip(a[:3], b[:3]):
         assert np.array_equal(np.asarray(u).view(np.uint8), np.asarray(v).view(np.uint8))
+
+
+def test_host_inputs_may_be_reused_when_the_call_returns():
+    """Host arrays are read before a query call returns, even while the
+    context's stream is still busy with earlier work: the caller may
+    overwrite them at once."""
+    n, k = 5000, 8
+    x, y = family("uniform", n, 46)
+    rng = np.random.default_rng(47)
+    iss = rng.permutation(n)[:1000].astype(np.int32)
+    first = iss.copy()
+    cx = rng.random(700, dtype=np.float32)
+    cy = rng.random(700, dtype=np.float32)
+    centres = (cx.copy(), cy.copy())
+    say("streams: host inputs overwritten right after the call")
+    with binding.Context(n, n, k) as c:
+        c.load_positions(x, y)
+        c.advance_tick()
+        with torch.cuda.stream(c.stream):
+            torch.cuda._sleep(SPIN_CYCLES)
+        c.query(k=k, issuers=iss)
+        iss[:] = rng.permutation(n)[:1000]
+        ids, d2, cnt, _ = c.fetch()
+        ei, ed, ec, _ = oracle.brute_knn(x, y, issuers=first, k=k, threads=16)
+        assert np.array_equal(cnt, ec)
+        assert np.array_equal(ids, ei) and np.array_equal(bits(d2), bits(ed))
+        with torch.cuda.stream(c.stream):
+            torch.cuda._sleep(SPIN_CYCLES)
+        c.query_points(cx, cy, k=k)
+        cx[:] = 0.5
+        cy[:] = 0.5
+        pids, pd2, pcnt, _ = c.fetch()
+    ei, ed, ec, _ = oracle.brute_knn_points(x, y, centres[0], centres[1], k=k)
+    assert np.array_equal(pcnt, ec)
+    assert np.array_equal(pids, ei) and np.array_equal(bits(pd2), bits(ed))
