@@ -210,8 +210,10 @@ MKNN_API int mknn_refit_tick(mknn_ctx *ctx);
  * then nq must equal n), centred on its position and excluding it, and asks
  * for ks[i] results (NULL = k_uniform for all).  Every k must be in
  * [1, k_max].  issuers and ks are int32 arrays of nq entries in host or
- * device memory per `where`; they are read before the call returns (host)
- * or once the stream reaches the query (device).  Results stay on the device,
+ * device memory per `where`; they are read before the call returns (host:
+ * the call copies them and waits for the context's stream to pass the
+ * copy, i.e. for the work enqueued before it) or once the stream reaches
+ * the query (device: no wait).  Results stay on the device,
  * owned by the context, until the next mknn_query.
  * Graph capture: a load/advance/query sequence with device inputs enqueues
  * kernels only, so it may be captured on the context's stream and
