@@ -459,7 +459,9 @@ class ReusePolicy:
     the host stays at most two ticks ahead while the last tick keeps the GPU
     busy (waiting for the last query instead would leave the GPU idle while
     the next tick is enqueued).  Queries older than the last full build are
-    ignored.  Needs a context created with timing=True."""
+    ignored.  A tick whose object count differs from the last full build's
+    rebuilds (a refit keeps that build's objects).  The caller enqueues one
+    query per tick after tick(); the context needs timing=True."""
 
     def __init__(self, factor=1.15, max_refits=None):
         self.factor = float(factor)
@@ -471,6 +473,7 @@ class ReusePolicy:
         self._last_build = -1   # tick of the last full build
         self._streak = 0        # refit ticks in a row
         self._last = None       # latest query time seen since that build
+        self._n_built = None    # object count of the last full build
 
     def tick(self, ctx, x, y):
         """Load the tick's positions and enqueue its index step."""
@@ -482,7 +485,8 @@ class ReusePolicy:
                     self.reference = t
                 else:
                     self._last = t
-        refit = (self._ticks > 0
+        n = len(x)
+        refit = (self._ticks > 0 and n == self._n_built
                  and (self.reference is None or self._last is None
                       or self._last <= self.factor * self.reference)
                  and (self.max_refits is None or self._streak < self.max_refits))
@@ -497,6 +501,7 @@ class ReusePolicy:
             self._streak = 0
             self._last_build = self._ticks
             self._last = None
+            self._n_built = n
         self._ticks += 1
         return "refit" if refit else "build"
 

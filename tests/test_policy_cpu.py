@@ -1,8 +1,9 @@
 """CPU: the index-reuse policy's decisions, on a scripted context (no GPU).
 It refits from the second tick on, keeps refitting while the query two
 ticks back stays within the factor of the query of the last full build,
-rebuilds when it does not or after max_refits refits in a row, and never
-waits for the last query (which would leave the GPU idle)."""
+rebuilds when it does not, after max_refits refits in a row or when the
+object count changes, and never waits for the last query (which would
+leave the GPU idle)."""
 from paper_1412_6170_amd import binding
 
 
@@ -30,10 +31,13 @@ class ScriptedContext:
         self.ticks += 1
 
 
+POS = [0.5] * 10   # ten objects; the scripted context ignores positions
+
+
 def run(times, n, **kw):
     ctx = ScriptedContext(times)
     pol = binding.ReusePolicy(**kw)
-    kinds = [pol.tick(ctx, None, None) for _ in range(n)]
+    kinds = [pol.tick(ctx, POS, POS) for _ in range(n)]
     return kinds, ctx, pol
 
 
@@ -64,3 +68,11 @@ def test_max_refits_in_a_row():
     kinds, ctx, pol = run({i: 1.0 for i in range(12)}, 9, factor=10.0, max_refits=3)
     assert kinds == ["build", "refit", "refit", "refit", "build", "refit", "refit", "refit",
                      "build"]
+
+
+def test_a_new_object_count_rebuilds():
+    ctx = ScriptedContext({i: 1.0 for i in range(10)})
+    pol = binding.ReusePolicy(factor=10.0)
+    sizes = [10, 10, 10, 12, 12, 9, 9]
+    kinds = [pol.tick(ctx, [0.5] * m, [0.5] * m) for m in sizes]
+    assert kinds == ["build", "refit", "refit", "build", "refit", "build", "refit"]
