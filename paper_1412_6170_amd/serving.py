@@ -83,7 +83,7 @@ class Server:
         scene.stream = self.torch.cuda.Stream()   # default priority
         scene.ctx = binding.Context(scene.n, scene.n, scene.k,
                                     leaf_capacity=scene.leaf_capacity,
-                                    stream=scene.stream.cuda_stream)
+                                    stream=scene.stream)
         self.resident += scene.footprint
         self.admissions += 1
         return True
