@@ -357,6 +357,11 @@ __global__ void k_morton(const float *__restrict__ x, const float *__restrict__ 
 // ---------------------------------------------------------------------------
 
 constexpr int kGhistItems = 16;  // keys per thread in the histogram kernel
+// Copies of the digit counts: workgroup b adds into copy b mod kGhistCopies,
+// so each count takes kGhistCopies times fewer global atomics from
+// different workgroups; a radix pass sums the copies of its digits.
+constexpr int kGhistCopies = 8;
+constexpr int kGhistStride = kMaxRadixPasses * kRadixBins;  // words per copy
 
 // Lanes of the wavefront (among `valid`) holding the same 8-bit digit d.
 __device__ __forceinline__ uint64_t digit_peers(uint32_t d, uint64_t valid)
@@ -389,6 +394,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_ghist(const uint32_t *__
         }
     }
     __syncthreads();
+    ghist += (blockIdx.x % kGhistCopies) * kGhistStride;
     for (int p = 0; p < passes; ++p) {
         const uint32_t c = s_h[p][threadIdx.x];
         if (c) atomicAdd(&ghist[p * kRadixBins + threadIdx.x], c);
@@ -471,7 +477,10 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_pass(
     // Offset of digit t: keys of smaller digits anywhere, plus keys of digit
     // t in earlier tiles.
     {
-        const uint32_t below = block_excl_scan<kSortThreads>(ghist[t], nullptr);
+        uint32_t count = 0;
+#pragma unroll
+        for (int c = 0; c < kGhistCopies; ++c) count += ghist[c * kGhistStride + t];
+        const uint32_t below = block_excl_scan<kSortThreads>(count, nullptr);
         const uint64_t before = lb_resolve(status + t, kRadixBins, tile, real, err, epoch);
         s_base[t] = below + (uint32_t)before;
     }
@@ -551,7 +560,7 @@ int launch_radix_sort(const SortBuffers &b, int64_t n, int bits, hipStream_t s, 
 int64_t workspace_words(int64_t n)
 {
     // ghist (u32) + tickets + err, then radix look-back words, then scans.
-    const int64_t small = (kMaxRadixPasses * kRadixBins + 16 + 8) / 2 + 8;
+    const int64_t small = (kGhistCopies * kGhistStride + 16 + 8) / 2 + 8;
     return small + (int64_t)kMaxRadixPasses * radix_tiles_bound(n) * kRadixBins +
            4 * scan_tiles(n) + 16;
 }
@@ -561,12 +570,12 @@ int64_t carve_workspace(const Workspace &ws, int64_t n, SortBuffers *sort, ScanS
 {
     uint64_t *p = ws.base;
     uint32_t *small = (uint32_t *)p;
-    sort->ghist = small;                                   // [4][256]
-    sort->tickets = small + kMaxRadixPasses * kRadixBins;  // [4]
+    sort->ghist = small;                                  // [copies][4][256]
+    sort->tickets = small + kGhistCopies * kGhistStride;  // [4]
     sort->err = err;
     sort->epoch = epoch;
     uint32_t *scan_tickets = sort->tickets + kMaxRadixPasses + 1;  // [n_scans]
-    p += (kMaxRadixPasses * kRadixBins + 16 + 8) / 2 + 8;
+    p += (kGhistCopies * kGhistStride + 16 + 8) / 2 + 8;
     sort->status = p;
     p += (int64_t)kMaxRadixPasses * radix_tiles(n) * kRadixBins;
     for (int i = 0; i < n_scans; ++i) {

@@ -82,7 +82,7 @@ constexpr int kMaxRadixPasses = 4;
 struct SortBuffers {
     uint32_t *keys[2];
     uint32_t *vals[2];
-    uint32_t *ghist;    // [kMaxRadixPasses][kRadixBins] global digit counts (zeroed)
+    uint32_t *ghist;    // global digit counts, [copies][kMaxRadixPasses][kRadixBins] (zeroed)
     uint64_t *status;   // [passes][tiles][kRadixBins] look-back words (zeroed)
     uint32_t *tickets;  // [kMaxRadixPasses] tile tickets (zeroed)
     uint32_t *err;      // raised to `epoch` if a look-back wait gives up
