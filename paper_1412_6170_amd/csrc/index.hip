@@ -801,11 +801,20 @@ __global__ __launch_bounds__(kScanThreads) void k_leaf_nodes(
         }
         __syncthreads();  // s_excl and the scan partials are reused by the next tile
     }
-    // Statistic only: one atomic per wavefront that saw leaves.
+    // Statistic only: one atomic per workgroup, skipped when the stored
+    // value is already as large (every workgroup targets the same word).
 #pragma unroll
     for (int d = 1; d < kWave; d <<= 1) deepest = max(deepest, __shfl_xor(deepest, d, kWave));
-    if ((threadIdx.x & (kWave - 1)) == 0 && deepest > 0)
-        atomicMax(&ctr->deepest, (epoch << 8) | (uint32_t)deepest);
+    __shared__ int s_deep[kScanThreads / kWave];
+    if ((threadIdx.x & (kWave - 1)) == 0) s_deep[threadIdx.x / kWave] = deepest;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kScanThreads / kWave; ++w) deepest = max(deepest, s_deep[w]);
+        const uint32_t v = (epoch << 8) | (uint32_t)deepest;
+        if (deepest > 0 &&
+            v > __hip_atomic_load(&ctr->deepest, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            atomicMax(&ctr->deepest, v);
+    }
 }
 
 __device__ __forceinline__ void node_box(uint32_t code, int l, Node &nd)

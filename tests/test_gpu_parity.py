@@ -183,8 +183,25 @@ def test_index_matches_oracle(kind, th, L):
         c.load_positions(x, y)
         c.advance_tick()
         got = c.index()
+        deepest = c.stats()["deepest_level"]
     for key in ("codes", "ids", "leaf_level", "leaf_prefix", "leaf_begin", "leaf_end"):
         assert same(got[key], exp[key]), key
+    assert deepest == int(np.max(exp["leaf_level"]))
+
+
+def test_deepest_level_per_build():
+    """The deepest leaf level is that of the latest build, also when it is
+    shallower than an earlier build's (the statistic is tagged with the
+    build's epoch, so an older, larger value does not stick)."""
+    deep = family("clustered", 20000, 25)
+    flat = family("uniform", 20000, 26)
+    with binding.Context(20000, 20000, 8, leaf_capacity=4, max_level=16) as c:
+        for (x, y), th in ((deep, 4), (flat, 4), (deep, 4), (flat, 4)):
+            c.set_leaf_capacity(th)
+            c.load_positions(x, y)
+            c.advance_tick()
+            exp = oracle.build_index(x, y, th, 16)
+            assert c.stats()["deepest_level"] == int(np.max(exp["leaf_level"]))
 
 
 def test_sort_tile_size_boundary():
