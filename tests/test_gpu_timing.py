@@ -102,3 +102,41 @@ def test_query_time_without_waiting():
         c.sync()
         with pytest.raises(binding.MknnError):
             c.query_time(0)      # timing off
+
+
+def test_work_counters_and_node_count():
+    """MKNN_FLAG_COUNTERS: per query, one count per wavefront of 64 queries,
+    at least one leaf swept and one candidate per wavefront, totals that
+    restart with reset_timing, and results bit-equal to a context without
+    counters.  The node count equals the number of distinct quadrants on
+    the paths from the root to every leaf of the oracle's index."""
+    from tests.helpers import family
+    import oracle
+    x, y = family("clustered", 30000, 48)
+    n, k, th, L = len(x), 16, 32, 16
+    exp = oracle.build_index(x, y, th, L)
+    quads = set()
+    for lev, pre in zip(exp["leaf_level"].tolist(), exp["leaf_prefix"].tolist()):
+        for l in range(lev + 1):
+            quads.add((l, pre >> (2 * (lev - l))))
+    with binding.Context(n, n, k, leaf_capacity=th, max_level=L, counters=True) as c, \
+            binding.Context(n, n, k, leaf_capacity=th, max_level=L) as p:
+        rows = []
+        for ctx in (c, p):
+            run(ctx, x, y, k)
+            rows.append(ctx.fetch())
+        for u, v in zip(rows[0][:3], rows[1][:3]):
+            assert np.array_equal(np.asarray(u).view(np.uint8), np.asarray(v).view(np.uint8))
+        st = c.stats()
+        say(st)
+        waves = -(-n // 64)
+        assert st["nodes"] == len(quads)
+        assert st["nq"] == n
+        assert st["wavefronts"] == waves
+        assert st["wave_leaf_sweeps"] >= waves and st["wave_candidate_steps"] >= waves
+        assert st["wave_node_visits"] > 0 and st["wave_merges"] >= waves
+        c.reset_timing()
+        issuers = np.arange(0, n, 3, dtype=np.int32)
+        c.query(k=k, issuers=torch.from_numpy(issuers).cuda())
+        c.sync()
+        assert c.stats()["wavefronts"] == -(-len(issuers) // 64)
