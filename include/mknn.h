@@ -149,8 +149,11 @@ typedef struct mknn_stats {
  */
 MKNN_API int mknn_create(const mknn_config *cfg, mknn_ctx **out);
 
-/* mknn_footprint -- device bytes mknn_create would allocate for cfg (no
- * device is touched), for admission decisions.  Errors: MKNN_E_INVAL. */
+/* mknn_footprint -- device bytes mknn_create requests for cfg (no device
+ * is touched), for admission decisions.  The runtime rounds each allocation
+ * up to its own granularity, so the device memory taken is slightly larger
+ * (about 2% at 4M objects, k_max 32); leave that margin in a budget.
+ * Errors: MKNN_E_INVAL. */
 MKNN_API int mknn_footprint(const mknn_config *cfg, int64_t *bytes);
 
 /* mknn_destroy -- wait for the context's work and free everything.  NULL is

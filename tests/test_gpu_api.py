@@ -1,0 +1,95 @@
+"""GPU: parts of the C ABI the binding's own calls do not reach --
+mknn_fetch into device buffers (uniform k, whose row offsets the library
+writes from the host, and variable k) and the device memory mknn_create
+takes against mknn_footprint."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from paper_1412_6170_amd import binding
+from tests.helpers import family
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    torch.cuda.set_device(0)
+    yield
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def fetch_to_device(ctx):
+    nq, ne = ctx.result_size()
+    ids = torch.full((max(ne, 1),), -7, dtype=torch.int32, device="cuda")
+    d2 = torch.full((max(ne, 1),), -7.0, dtype=torch.float32, device="cuda")
+    cnt = torch.full((max(nq, 1),), -7, dtype=torch.int32, device="cuda")
+    off = torch.full((nq + 1,), -7, dtype=torch.int64, device="cuda")
+    torch.cuda.synchronize()
+    rc = binding.lib().mknn_fetch(ctx._h, ptr(ids), ptr(d2), ptr(cnt), ptr(off),
+                                  binding.MKNN_DEVICE)
+    assert rc == 0, binding.lib().mknn_last_error(ctx._h)
+    return (ids[:ne].cpu().numpy(), d2[:ne].cpu().numpy(), cnt[:nq].cpu().numpy(),
+            off.cpu().numpy())
+
+
+def same_bytes(a, b):
+    return np.array_equal(np.ascontiguousarray(a).view(np.uint8),
+                          np.ascontiguousarray(b).view(np.uint8))
+
+
+@pytest.mark.parametrize("variable_k", [False, True])
+def test_fetch_into_device_buffers(variable_k):
+    n, k = 6000, 16
+    x, y = family("clustered", n, 51)
+    rng = np.random.default_rng(52)
+    say("api: device fetch, variable k=%s" % variable_k)
+    with binding.Context(n, n, k) as c:
+        c.load_positions(x, y)
+        c.advance_tick()
+        if variable_k:
+            iss = rng.permutation(n)[:2500].astype(np.int32)
+            ks = rng.integers(1, k + 1, len(iss)).astype(np.int32)
+            c.query(issuers=iss, ks=ks)
+        else:
+            c.query(k=k)
+        hi, hd, hc, ho = c.fetch()
+        di, dd, dc, do = fetch_to_device(c)
+    assert same_bytes(np.ravel(hi), di) and same_bytes(np.ravel(hd), dd) and same_bytes(hc, dc)
+    if variable_k:
+        assert same_bytes(ho, do)
+    else:
+        assert np.array_equal(do, np.arange(n + 1, dtype=np.int64) * k)
+
+
+def test_create_takes_the_reported_footprint():
+    n, k, th = 4_000_000, 32, 64
+    fp = binding.footprint(n_max=n, k_max=k, leaf_capacity=th)
+    torch.cuda.synchronize()
+    free0, _ = torch.cuda.mem_get_info()
+    c = binding.Context(n, n, k, leaf_capacity=th)
+    torch.cuda.synchronize()
+    free1, _ = torch.cuda.mem_get_info()
+    c.close()
+    torch.cuda.synchronize()
+    free2, _ = torch.cuda.mem_get_info()
+    taken, given_back = free0 - free1, free2 - free1
+    say("api: footprint %d B, create took %d B, destroy gave back %d B" % (fp, taken, given_back))
+    # The runtime rounds allocations up and may carve small ones from
+    # memory it already holds: the context's large buffers decide, within
+    # a few tens of MiB.
+    slack = 64 << 20
+    assert fp - slack <= taken <= fp * 1.02 + slack
+    assert given_back >= taken - slack
