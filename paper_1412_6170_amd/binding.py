@@ -229,7 +229,11 @@ class Context:
                 raise ValueError("device arrays must be on the context's device (%d)"
                                  % self.cfg.device)
         cur = torch.cuda.current_stream(self.cfg.device)
-        if cur.cuda_stream != self._tstream.cuda_stream:
+        # Nothing to wait for when the caller's stream is the context's, or
+        # has already finished everything enqueued on it (a capturing
+        # stream cannot be asked, so it always gets the event).
+        if cur.cuda_stream != self._tstream.cuda_stream and (
+                torch.cuda.is_current_stream_capturing() or not cur.query()):
             hip = _hip()
             rc = hip.hipEventRecord(self._order_ev, ctypes.c_void_p(cur.cuda_stream))
             if rc == 0:

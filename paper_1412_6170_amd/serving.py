@@ -25,7 +25,8 @@ from . import binding
 
 class Scene:
     def __init__(self, sid, positions, k, leaf_capacity=0):
-        """positions: list of (x, y) device tensors, one per tick."""
+        """positions: list of (x, y) device tensors, one per tick; they
+        stay unchanged while the scene is served."""
         self.sid = sid
         self.positions = positions
         self.n = int(positions[0][0].numel())
@@ -91,9 +92,13 @@ class Server:
     def _launch(self, req, now):
         sc = req.scene
         x, y = sc.positions[req.tick % len(sc.positions)]
-        sc.ctx.load_positions(x, y)
-        sc.ctx.advance_tick()
-        sc.ctx.query(k=sc.k, nq=sc.n)
+        # Positions are complete (run() synchronised before serving), so the
+        # tick is enqueued from the scene's own stream: the binding has no
+        # other stream to order it after.
+        with self.torch.cuda.stream(sc.stream):
+            sc.ctx.load_positions(x, y)
+            sc.ctx.advance_tick()
+            sc.ctx.query(k=sc.k, nq=sc.n)
         ev = self.torch.cuda.Event()
         ev.record(sc.stream)
         req.event = ev
@@ -106,6 +111,10 @@ class Server:
         """arrivals: list of (t_seconds, scene_id, tick), t relative to the
         start.  Returns the completed requests in completion order."""
         arrivals = sorted(arrivals, key=lambda a: a[0])
+        # Scene positions may still be being written by earlier work on any
+        # stream: finish it once, so that ticks can be enqueued from the
+        # scenes' own streams with nothing else to wait for.
+        self.torch.cuda.synchronize()
         pending = collections.deque()
         inflight = []
         done = []
