@@ -149,10 +149,10 @@ typedef struct mknn_stats {
  */
 MKNN_API int mknn_create(const mknn_config *cfg, mknn_ctx **out);
 
-/* mknn_footprint -- device bytes mknn_create requests for cfg (no device
- * is touched), for admission decisions.  The runtime rounds each allocation
- * up to its own granularity, so the device memory taken is slightly larger
- * (about 2% at 4M objects, k_max 32); leave that margin in a budget.
+/* mknn_footprint -- device bytes mknn_create takes for cfg (no device is
+ * touched), for admission decisions: each buffer of 2 MiB or more rounded
+ * up to whole 2 MiB pages, as the runtime maps them, smaller ones to 256
+ * bytes (the runtime may carve those from memory it already holds).
  * Errors: MKNN_E_INVAL. */
 MKNN_API int mknn_footprint(const mknn_config *cfg, int64_t *bytes);
 

@@ -352,8 +352,11 @@ int mknn_footprint(const mknn_config *cfg, int64_t *bytes)
     int64_t total = 0;
     for_each_buffer(&tmp, [&](auto &p, int64_t count) {
         if (count < 1) count = 1;
-        // hipMalloc rounds small allocations up; count whole 256-byte units.
-        total += (int64_t)(((size_t)count * sizeof(*p) + 255) / 256 * 256);
+        // The runtime maps buffers of 2 MiB or more in whole 2 MiB pages;
+        // smaller ones are counted in 256-byte units.
+        const size_t b = (size_t)count * sizeof(*p);
+        const size_t unit = b >= ((size_t)2 << 20) ? ((size_t)2 << 20) : 256;
+        total += (int64_t)((b + unit - 1) / unit * unit);
     });
     *bytes = total;
     return MKNN_OK;

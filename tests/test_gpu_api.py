@@ -87,9 +87,9 @@ def test_create_takes_the_reported_footprint():
     free2, _ = torch.cuda.mem_get_info()
     taken, given_back = free0 - free1, free2 - free1
     say("api: footprint %d B, create took %d B, destroy gave back %d B" % (fp, taken, given_back))
-    # The runtime rounds allocations up and may carve small ones from
-    # memory it already holds: the context's large buffers decide, within
-    # a few tens of MiB.
-    slack = 64 << 20
-    assert fp - slack <= taken <= fp * 1.02 + slack
-    assert given_back >= taken - slack
+    # Large buffers are mapped in whole 2 MiB pages, which the footprint
+    # counts; the few small ones may come from memory the runtime holds.
+    slack = 4 << 20
+    assert fp - slack <= taken <= fp + slack
+    # The runtime may keep a few MiB mapped after the buffers are freed.
+    assert given_back >= taken - (16 << 20)
