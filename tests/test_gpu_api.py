@@ -93,3 +93,21 @@ def test_create_takes_the_reported_footprint():
     assert fp - slack <= taken <= fp + slack
     # The runtime may keep a few MiB mapped after the buffers are freed.
     assert given_back >= taken - (16 << 20)
+
+
+def test_readme_python_example():
+    """The Python usage example in README.md runs as written and returns
+    the exact rows."""
+    import os
+    import re
+    import oracle
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    text = open(os.path.join(root, "README.md")).read()
+    block = re.search(r"```python\n(.*?)```", text, re.S).group(1)
+    n = 3000
+    x, y = family("clustered", n, 53)
+    env = {"n": n, "x": x, "y": y}
+    exec(compile(block, "README.md", "exec"), env)
+    ei, ed, ec, _ = oracle.brute_knn(x, y, k=32, threads=16)
+    assert np.array_equal(env["ids"], ei) and np.array_equal(env["counts"], ec)
+    assert same_bytes(env["d2"], ed)
