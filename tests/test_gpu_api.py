@@ -111,3 +111,51 @@ def test_readme_python_example():
     ei, ed, ec, _ = oracle.brute_knn(x, y, k=32, threads=16)
     assert np.array_equal(env["ids"], ei) and np.array_equal(env["counts"], ec)
     assert same_bytes(env["d2"], ed)
+
+
+def test_autotuner_picks_a_timed_candidate_and_results_stay_exact():
+    """binding.autotune_leaf_capacity times every candidate with the
+    library's events, returns the fastest, leaves the context at it, and
+    the ticks before and after tuning give the exact rows (the leaf
+    capacity changes only the time)."""
+    import oracle
+    from paper_1412_6170_amd import workloads
+    w = workloads.clustered_1m(n=60_000, ticks=4)
+    k = 16
+    dev = []
+    for t in range(w.ticks):
+        x, y, _, _, _ = w.tick(t)
+        dev.append((x, y, torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()))
+    cands = (16, 64, 256)
+    with binding.Context(w.n, w.n, k, leaf_capacity=min(cands), timing=True) as c:
+        def run_tick(i):
+            _, _, xd, yd = dev[i % len(dev)]
+            c.load_positions(xd, yd)
+            c.advance_tick()
+            c.query(k=k)
+
+        best, times = binding.autotune_leaf_capacity(c, run_tick, cands, repeats=2)
+        say("api: autotuner chose %d from %s" % (best, times))
+        assert best in cands and set(times) == set(cands)
+        assert all(v > 0 for v in times.values()) and times[best] == min(times.values())
+        run_tick(1)
+        ids, d2, cnt, _ = c.fetch()
+        assert c.stats()["leaf_capacity"] == best
+    x, y = dev[1][0], dev[1][1]
+    sample = np.arange(0, w.n, 101, dtype=np.int32)
+    ei, ed, ec, _ = oracle.brute_knn(x, y, issuers=sample, k=k, threads=16)
+    assert np.array_equal(ids[sample], ei) and same_bytes(d2[sample], ed)
+    assert np.array_equal(cnt[sample], ec)
+
+
+def test_knn_tick_helper():
+    import oracle
+    x, y = family("duplicates", 2500, 54)
+    rng = np.random.default_rng(55)
+    iss = rng.permutation(2500)[:700].astype(np.int32)
+    ks = rng.integers(1, 20, len(iss)).astype(np.int32)
+    got = binding.knn_tick(x, y, issuers=iss, ks=ks)
+    exp = oracle.brute_knn(x, y, issuers=iss, ks=ks, threads=16)
+    for u, v in zip(got[:3], exp[:3]):
+        assert same_bytes(np.asarray(u), np.asarray(v))
+    assert np.array_equal(got[3], exp[3])
