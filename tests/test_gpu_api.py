@@ -159,3 +159,36 @@ def test_knn_tick_helper():
     for u, v in zip(got[:3], exp[:3]):
         assert same_bytes(np.asarray(u), np.asarray(v))
     assert np.array_equal(got[3], exp[3])
+
+
+def test_two_contexts_on_two_host_threads():
+    """Separate contexts are independent: two host threads, each with its
+    own context, run ticks at the same time and both get the exact rows."""
+    import threading
+    import oracle
+    inputs = [family(kind, 8000, 56 + i) for i, kind in enumerate(("clustered", "uniform"))]
+    got = [None, None]
+    errors = []
+
+    def worker(i):
+        try:
+            x, y = inputs[i]
+            with binding.Context(len(x), len(x), 8) as c:
+                for _ in range(3):
+                    c.load_positions(torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda())
+                    c.advance_tick()
+                    c.query(k=8)
+                    got[i] = c.fetch()
+        except Exception as e:  # reported by the main thread
+            errors.append(e)
+
+    threads = [threading.Thread(target=worker, args=(i,)) for i in range(2)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=60)
+    assert not any(t.is_alive() for t in threads) and not errors, errors
+    for i, (x, y) in enumerate(inputs):
+        ei, ed, ec, _ = oracle.brute_knn(x, y, k=8, threads=16)
+        assert np.array_equal(got[i][0], ei) and same_bytes(got[i][1], ed)
+        assert np.array_equal(got[i][2], ec)
