@@ -4,6 +4,8 @@ The checks here restate properties of the exact k-NN result (Definition 1 of
 arXiv 1412.6170 with ties broken by ascending id); they do not call the
 oracle, so they can pin it.
 """
+import zlib
+
 import numpy as np
 
 CLAMP_HI = np.float32(1.0 - 2.0 ** -24)
@@ -14,8 +16,10 @@ def f32(a):
 
 
 def family(kind, n, seed):
-    """Tiny input families that stress different parts of the search."""
-    rng = np.random.default_rng([7, seed, n, hash(kind) % 1000])
+    """Tiny input families that stress different parts of the search.  The
+    seed mixes in a CRC of the family name (stable across processes, unlike
+    Python's salted str hash), so every input replays from its seed."""
+    rng = np.random.default_rng([7, seed, n, zlib.crc32(kind.encode()) % 1000])
     if kind == "uniform":
         x, y = rng.random(n, dtype=np.float32), rng.random(n, dtype=np.float32)
     elif kind == "clustered":

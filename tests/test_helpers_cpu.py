@@ -47,3 +47,34 @@ def test_rejects_planted_mistakes(exact, how):
     x, y, k, ids, d2, cnt = plant(exact, how)
     with pytest.raises(AssertionError):
         check_rows_vectorized(x, y, np.arange(len(x)), ids, d2, cnt, k)
+
+
+def test_families_replay_across_processes():
+    """Every input family draws the same values in a fresh interpreter (the
+    seed must not depend on Python's per-process string hash)."""
+    import hashlib
+    import os
+    import subprocess
+    import sys
+
+    from tests.helpers import FAMILIES
+
+    def digest_here():
+        h = hashlib.sha256()
+        for kind in FAMILIES:
+            x, y = family(kind, 257, 9)
+            h.update(x.tobytes())
+            h.update(y.tobytes())
+        return h.hexdigest()
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import hashlib\nfrom tests.helpers import FAMILIES, family\nh = hashlib.sha256()\n"
+            "for kind in FAMILIES:\n    x, y = family(kind, 257, 9)\n"
+            "    h.update(x.tobytes())\n    h.update(y.tobytes())\nprint(h.hexdigest())\n")
+    outs = set()
+    for salt in ("1", "2"):
+        env = dict(os.environ, PYTHONHASHSEED=salt)
+        r = subprocess.run([sys.executable, "-c", code], cwd=root, env=env, check=True,
+                           capture_output=True, text=True)
+        outs.add(r.stdout.strip())
+    assert outs == {digest_here()}
