@@ -253,8 +253,14 @@ MKNN_API int mknn_query_points(mknn_ctx *ctx, const float *qx, const float *qy,
 
 /*
  * mknn_fetch -- synchronise, then copy the last query's results into
- * caller-owned buffers (host or device per `where`).  Rows are in query
- * order.  Uniform k: ids and d2 are dense row-major [nq][k]; offsets may be
+ * caller-owned buffers (host or device per `where`).  The layout is the
+ * paper's k-NN result set (Sec. 3, "k-NN queries result set layout", and
+ * Fig. 1): one linear list of k slots per query, query after query, each
+ * slot an (object id, distance) pair -- the ID and DIST outputs of Alg. 1
+ * -- with the number of valid slots per query kept apart (Alg. 1's
+ * NUMRES).  Here the ids and the squared distances are two parallel
+ * arrays of slots, and a list is sorted ascending by (d2, id).  Rows are
+ * in query order.  Uniform k: ids and d2 are dense row-major [nq][k]; offsets may be
  * NULL.  Variable k: row i occupies entries offsets[i] .. offsets[i+1]-1
  * (offsets has nq+1 int64 entries, offsets[i+1]-offsets[i] = ks[i]).
  * counts[i] = min(k_i, n-1).  Any of ids, d2, counts, offsets may be NULL

@@ -107,7 +107,9 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *total)
 }
 
 // ---------------------------------------------------------------------------
-// Decoupled look-back: tile t publishes its aggregate, then walks back over
+// Decoupled look-back (the single-pass prefix scan of Merrill and Garland,
+// "Single-pass Parallel Prefix Scan with Decoupled Look-back", NVIDIA
+// technical report NVR-2016-002): tile t publishes its aggregate, then walks back over
 // tiles t-1, t-2, ... adding aggregates until it meets an inclusive prefix,
 // and publishes its own inclusive prefix.  A word holds a 2-bit flag and a
 // 62-bit value, written and read as one 64-bit atomic.  Tiles take tickets

@@ -85,3 +85,25 @@ def test_valu_issue_fraction():
     assert got["bound"] == "alu"
     assert abs(got["frac"] - m["valu_insts"] * 64 / (ms * 1e-3) / (256 * 4 * 16 * 2.4e9)) < 1e-12
     assert bench.valu_issue("uniform_10k", m["leaf_capacity"], 16, ms) is None
+
+
+def test_roofline_names_the_closer_roof():
+    m = bench.MEASURED_TRAFFIC
+    L = m.get("max_level", 16)
+    r = bench.roofline_entry(m["workload"], m["leaf_capacity"], L, 32, 0.44, 272_000_000)
+    assert abs(r["hbm_frac" if r["bound"] == "alu" else "frac"]
+               - 272_000_000 / 0.44e-3 / 8e12) < 1e-9
+    v = bench.valu_issue(m["workload"], m["leaf_capacity"], L, 0.44)
+    if v is None:
+        assert r["bound"] == "hbm"
+    else:
+        assert r["bound"] == ("alu" if v["frac"] > r.get("hbm_frac", r["frac"]) else "hbm")
+    # A configuration without a stored instruction count falls back to HBM.
+    r2 = bench.roofline_entry("uniform_10k", 32, 16, 8, 0.06, 1_000_000)
+    assert r2["bound"] == "hbm" and r2["unit"] == "GB/s"
+
+
+def test_cpu_model_reads_the_host():
+    cpu = bench.cpu_model()
+    assert cpu["logical_cpus"] >= 1 and isinstance(cpu["model"], str)
+    assert bench.host_threads() >= 1
