@@ -73,10 +73,14 @@ def code_only(text):
     return " ".join(text.split())
 
 
+DIGEST_FILES = ("query.hip", "query_wave.hip", "query.hpp", "query_device.hpp",
+                "mknn_internal.hpp")
+
+
 def query_source_digest(read=None):
     import hashlib
     h = hashlib.sha256()
-    for f in ("query.hip", "query.hpp", "mknn_internal.hpp"):
+    for f in DIGEST_FILES:
         if read is None:
             with open(os.path.join(ROOT, "paper_1412_6170_amd", "csrc", f)) as fh:
                 text = fh.read()

@@ -74,7 +74,18 @@ extern "C" {
 #define MKNN_DEVICE 1
 
 /* Largest k any query may ask for. */
-#define MKNN_K_LIMIT 128
+#define MKNN_K_LIMIT 1024
+
+/* Sweep flavours (Sec. 4.2.1, distance computations).  LANE is the
+ * "cached writes" flavour: one query per lane, its best keys in that lane's
+ * registers (k <= 128).  WAVE is the "coalesced writes" flavour: one query
+ * per wavefront, candidates checked by the lanes side by side, list updates
+ * orchestrated with ballots through an LDS buffer, rows written by
+ * consecutive lanes (any k up to MKNN_K_LIMIT).  AUTO takes LANE up to
+ * k = 128 and WAVE above.  Results are the same in every flavour. */
+#define MKNN_SWEEP_AUTO 0
+#define MKNN_SWEEP_LANE 1
+#define MKNN_SWEEP_WAVE 2
 
 /* mknn_config.flags */
 /* Record per-phase device times (mknn_stats): HIP events on the context's
@@ -90,6 +101,9 @@ extern "C" {
  * when k is drawn independently per query, each class is sparse in space
  * and one pass is faster.  Results are the same either way. */
 #define MKNN_FLAG_GROUP_K 4
+/* Answer every query with the one-query-per-wavefront flavour
+ * (MKNN_SWEEP_WAVE) instead of MKNN_SWEEP_AUTO. */
+#define MKNN_FLAG_SWEEP_WAVE 8
 
 typedef struct mknn_ctx mknn_ctx;
 
@@ -314,6 +328,35 @@ MKNN_API int mknn_get_stats(const mknn_ctx *ctx, mknn_stats *out);
  * th.  Errors: MKNN_E_INVAL (th < 1), MKNN_E_CAPACITY.
  */
 MKNN_API int mknn_set_leaf_capacity(mknn_ctx *ctx, int32_t th);
+
+/*
+ * Tuning knobs of a context, for an autotuner (results never depend on
+ * them).  leaf_capacity is th (Sec. 4.1); max_level is l_max (Sec. 4.1,
+ * 1..16); sweep is an MKNN_SWEEP_* flavour (LANE applies to k <= 128;
+ * larger k always use WAVE); group_k != 0 behaves as MKNN_FLAG_GROUP_K
+ * (variable-k queries answered per k class, lane flavour only).  The
+ * index settings take effect at the next mknn_advance_tick, the sweep
+ * settings at the next query.
+ */
+typedef struct mknn_schedule {
+    int32_t leaf_capacity;
+    int32_t max_level;
+    int32_t sweep;
+    int32_t group_k;
+} mknn_schedule;
+
+/* mknn_get_schedule -- the settings in force.  Errors: MKNN_E_INVAL. */
+MKNN_API int mknn_get_schedule(const mknn_ctx *ctx, mknn_schedule *out);
+
+/*
+ * mknn_set_schedule -- change every setting at once.  The node tables were
+ * sized at mknn_create; a leaf capacity below, or a maximum level above,
+ * the configured ones may need more nodes: such a schedule returns
+ * MKNN_E_CAPACITY unless the tables still fit.  Errors: MKNN_E_INVAL
+ * (leaf_capacity < 1, max_level outside 1..16, unknown sweep),
+ * MKNN_E_CAPACITY.  On error nothing changes.
+ */
+MKNN_API int mknn_set_schedule(mknn_ctx *ctx, const mknn_schedule *s);
 
 /* mknn_reset_timing -- forget the device times and counters recorded so far
  * (the means and totals in mknn_stats restart). */

@@ -19,7 +19,12 @@ MKNN_DEVICE = 1
 MKNN_FLAG_TIMING = 1
 MKNN_FLAG_COUNTERS = 2
 MKNN_FLAG_GROUP_K = 4
-MKNN_K_LIMIT = 128
+MKNN_FLAG_SWEEP_WAVE = 8
+MKNN_K_LIMIT = 1024
+MKNN_SWEEP_AUTO = 0
+MKNN_SWEEP_LANE = 1
+MKNN_SWEEP_WAVE = 2
+SWEEPS = {"auto": MKNN_SWEEP_AUTO, "lane": MKNN_SWEEP_LANE, "wave": MKNN_SWEEP_WAVE}
 STATUS = {0: "MKNN_OK", -1: "MKNN_E_INVAL", -2: "MKNN_E_RANGE", -3: "MKNN_E_STATE",
           -4: "MKNN_E_CAPACITY", -5: "MKNN_E_NOMEM", -6: "MKNN_E_DEVICE"}
 
@@ -44,6 +49,11 @@ class Stats(ctypes.Structure):
                 ("wave_node_visits", ctypes.c_int64), ("wave_leaf_sweeps", ctypes.c_int64),
                 ("wavefronts", ctypes.c_int64), ("refits", ctypes.c_int64),
                 ("drift", ctypes.c_float), ("reserved2", ctypes.c_float)]
+
+
+class Schedule(ctypes.Structure):
+    _fields_ = [("leaf_capacity", ctypes.c_int32), ("max_level", ctypes.c_int32),
+                ("sweep", ctypes.c_int32), ("group_k", ctypes.c_int32)]
 
 
 class MknnError(RuntimeError):
@@ -89,6 +99,8 @@ def lib():
             "mknn_status_str": ([_i32], ctypes.c_char_p),
             "mknn_default_leaf_capacity": ([_i32], _i32),
             "mknn_footprint": ([ctypes.POINTER(Config), ctypes.POINTER(_i64)], _i32),
+            "mknn_get_schedule": ([_vp, ctypes.POINTER(Schedule)], _i32),
+            "mknn_set_schedule": ([_vp, ctypes.POINTER(Schedule)], _i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -129,7 +141,7 @@ def default_leaf_capacity(k):
 
 
 def make_config(n_max, q_max=None, k_max=32, leaf_capacity=0, max_level=0, k_hint=0, device=0,
-                stream=None, timing=False, counters=False, group_k=False):
+                stream=None, timing=False, counters=False, group_k=False, sweep_wave=False):
     cfg = Config()
     cfg.device = device
     cfg.leaf_capacity = int(leaf_capacity)
@@ -140,7 +152,8 @@ def make_config(n_max, q_max=None, k_max=32, leaf_capacity=0, max_level=0, k_hin
     cfg.stream = stream
     cfg.k_hint = int(k_hint)
     cfg.flags = ((MKNN_FLAG_TIMING if timing else 0) | (MKNN_FLAG_COUNTERS if counters else 0)
-                 | (MKNN_FLAG_GROUP_K if group_k else 0))
+                 | (MKNN_FLAG_GROUP_K if group_k else 0)
+                 | (MKNN_FLAG_SWEEP_WAVE if sweep_wave else 0))
     return cfg
 
 
@@ -175,7 +188,8 @@ class Context:
     call."""
 
     def __init__(self, n_max, q_max=None, k_max=32, leaf_capacity=0, max_level=0, k_hint=0,
-                 device=0, stream=None, timing=False, counters=False, group_k=False):
+                 device=0, stream=None, timing=False, counters=False, group_k=False,
+                 sweep_wave=False):
         self._h = None
         self._order_ev = None
         import torch
@@ -195,7 +209,7 @@ class Context:
             ts = torch.cuda.Stream(device=device)   # default priority
         self._tstream = ts
         cfg = make_config(n_max, q_max, k_max, leaf_capacity, max_level, k_hint, device,
-                          ts.cuda_stream, timing, counters, group_k)
+                          ts.cuda_stream, timing, counters, group_k, sweep_wave)
         self.cfg = cfg
         h = _vp()
         rc = lib().mknn_create(ctypes.byref(cfg), ctypes.byref(h))
@@ -422,6 +436,26 @@ class Context:
     def set_leaf_capacity(self, th):
         self._check(lib().mknn_set_leaf_capacity(self._h, int(th)))
 
+    def schedule(self):
+        """The tuning settings in force: leaf_capacity, max_level, sweep
+        ("auto", "lane" or "wave") and group_k."""
+        sc = Schedule()
+        self._check(lib().mknn_get_schedule(self._h, ctypes.byref(sc)))
+        names = {v: k for k, v in SWEEPS.items()}
+        return {"leaf_capacity": sc.leaf_capacity, "max_level": sc.max_level,
+                "sweep": names[sc.sweep], "group_k": bool(sc.group_k)}
+
+    def set_schedule(self, leaf_capacity=None, max_level=None, sweep=None, group_k=None):
+        """Change tuning settings (None: keep); results never depend on
+        them."""
+        cur = self.schedule()
+        sc = Schedule()
+        sc.leaf_capacity = int(cur["leaf_capacity"] if leaf_capacity is None else leaf_capacity)
+        sc.max_level = int(cur["max_level"] if max_level is None else max_level)
+        sc.sweep = SWEEPS[cur["sweep"] if sweep is None else sweep]
+        sc.group_k = int(cur["group_k"] if group_k is None else bool(group_k))
+        self._check(lib().mknn_set_schedule(self._h, ctypes.byref(sc)))
+
     def stats_ready(self):
         """True once the context has run a query (stats then describe it)."""
         return getattr(self, "_queried", False)
@@ -540,14 +574,67 @@ def autotune_leaf_capacity(ctx, run_tick, candidates, repeats=3):
     return best, times
 
 
-def knn_tick(x, y, k=None, issuers=None, ks=None, leaf_capacity=0, max_level=0, k_max=None):
+def autotune_schedule(ctx, run_tick, leaf_capacities, max_levels=(), sweeps=(), group_k=(),
+                      repeats=3, rounds=2):
+    """Pick the schedule with the shortest device time per tick, one
+    dimension at a time (coordinate descent over leaf capacity, maximum
+    level, sweep flavour and k grouping, `rounds` passes; an empty list
+    leaves that dimension as it is).
+
+    ctx must have been created with timing enabled and with node tables
+    that fit every candidate (the smallest leaf capacity and the largest
+    maximum level).  run_tick(i) enqueues tick i (load, advance, query) on
+    the context.  A setting runs one untimed tick, then `repeats` timed
+    ticks; the mean of the library's build + query device times decides.
+    Results never depend on the schedule, only the time does.  Returns
+    (best schedule dict, {str(setting): ms})."""
+    times = {}
+    i = [0]
+
+    def measure(**kw):
+        key = tuple(sorted(kw.items()))
+        if key in times:
+            return times[key]
+        ctx.set_schedule(**kw)
+        run_tick(i[0])
+        i[0] += 1
+        ctx.sync()
+        ctx.reset_timing()
+        for _ in range(repeats):
+            run_tick(i[0])
+            i[0] += 1
+        ctx.sync()
+        st = ctx.stats()
+        times[key] = st["ms_build_mean"] + st["ms_query_mean"]
+        return times[key]
+
+    best = ctx.schedule()
+    dims = [("leaf_capacity", list(leaf_capacities)), ("max_level", list(max_levels)),
+            ("sweep", list(sweeps)), ("group_k", [bool(g) for g in group_k])]
+    for _ in range(rounds):
+        for name, values in dims:
+            if not values:
+                continue
+            trial = {}
+            for v in values:
+                cand = dict(best, **{name: v})
+                trial[v] = measure(**cand)
+            best = dict(best, **{name: min(trial, key=trial.get)})
+    ctx.set_schedule(**best)
+    ctx.sync()
+    ctx.reset_timing()
+    return best, {", ".join("%s=%s" % kv for kv in k): v for k, v in times.items()}
+
+
+def knn_tick(x, y, k=None, issuers=None, ks=None, leaf_capacity=0, max_level=0, k_max=None,
+             sweep_wave=False):
     """One tick through a fresh context: load, advance, query, fetch."""
     n = len(x)
     nq = n if issuers is None else len(issuers)
     if k_max is None:
         k_max = int(k) if ks is None else int(np.max(ks)) if len(ks) else 1
     with Context(max(n, 1), max(nq, 1), k_max, leaf_capacity=leaf_capacity,
-                 max_level=max_level) as c:
+                 max_level=max_level, sweep_wave=sweep_wave) as c:
         c.load_positions(x, y)
         c.advance_tick()
         c.query(k=k, issuers=issuers, ks=ks, nq=nq)

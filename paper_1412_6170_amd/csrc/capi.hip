@@ -18,6 +18,8 @@ using namespace mknn;
 struct mknn_ctx {
     mknn_config cfg{};
     int th = 0, L = 16, k_max = 1;
+    int sweep = MKNN_SWEEP_AUTO;  // sweep flavour (mknn_schedule)
+    bool group_k = false;         // variable k answered per k class
     hipStream_t stream = nullptr;
     bool own_stream = false;
     bool dead = false;         // sticky device error
@@ -276,6 +278,8 @@ void configure(mknn_ctx *c, const mknn_config *cfg)
     c->k_max = cfg->k_max;
     const int kh = cfg->k_hint ? cfg->k_hint : cfg->k_max;
     c->th = cfg->leaf_capacity ? cfg->leaf_capacity : mknn_default_leaf_capacity(kh);
+    c->sweep = (cfg->flags & MKNN_FLAG_SWEEP_WAVE) ? MKNN_SWEEP_WAVE : MKNN_SWEEP_AUTO;
+    c->group_k = (cfg->flags & MKNN_FLAG_GROUP_K) != 0;
     size_context(c);
 }
 
@@ -297,6 +301,19 @@ int mark_main(mknn_ctx *c, bool prepared)
     if (!((c->cfg.flags & MKNN_FLAG_TIMING) && c->have_ring)) return MKNN_OK;
     c->main_is_start[c->query_slot % mknn_ctx::kRing] = !prepared;
     return prepared ? mark(c, 3) : MKNN_OK;
+}
+
+// The one-query-per-wavefront flavour answers every k above the lane
+// kernel's 128 keys, and any k when the schedule asks for it.
+bool use_wave_sweep(const mknn_ctx *c, int kmax_call)
+{
+    return kmax_call > 128 || c->sweep == MKNN_SWEEP_WAVE;
+}
+
+void launch_sweep(const mknn_ctx *c, const QueryArgs &qa, int kmax_call)
+{
+    if (use_wave_sweep(c, kmax_call)) launch_knn_wave(qa, k_class_wave(kmax_call), c->stream);
+    else launch_knn(qa, k_class(kmax_call), c->stream);
 }
 
 }  // namespace
@@ -668,7 +685,7 @@ int mknn_query_points(mknn_ctx *c, const float *qx, const float *qy, const int32
     }
     rc = mark_main(c, nq > 0 || ks != nullptr);
     if (rc) return rc;
-    launch_knn(qa, k_class(kmax_call), c->stream);
+    launch_sweep(c, qa, kmax_call);
     rc = check_launch(c, "k-NN query");
     if (!rc) rc = mark(c, 4);
     if (rc) return rc;
@@ -741,8 +758,8 @@ int mknn_query(mknn_ctx *c, const int32_t *issuers, const int32_t *ks, int64_t n
     // (sorted by class, then by position) and each class runs with its own
     // list size, as long as class and position fit one 32-bit sort key.
     const int pbits = pos_bits(c->n);
-    const bool grouped =
-        (c->cfg.flags & MKNN_FLAG_GROUP_K) && d_ks && nq > 0 && pbits + 3 <= 32;
+    const bool grouped = c->group_k && d_ks && nq > 0 && pbits + 3 <= 32 &&
+                         !use_wave_sweep(c, kmax_call);
     if ((d_iss || grouped) && nq > 0 && !c->inv_ready) {
         launch_inverse(c->ix, c->n, c->stream);
         c->inv_ready = true;
@@ -800,7 +817,7 @@ int mknn_query(mknn_ctx *c, const int32_t *issuers, const int32_t *ks, int64_t n
             launch_knn(qa, 8 << cls, c->stream);
         }
     } else {
-        launch_knn(qa, k_class(kmax_call), c->stream);
+        launch_sweep(c, qa, kmax_call);
     }
     rc = check_launch(c, "k-NN query");
     if (!rc) rc = mark(c, 4);
@@ -940,6 +957,34 @@ int mknn_set_leaf_capacity(mknn_ctx *c, int32_t th)
         return fail(c, MKNN_E_CAPACITY, "leaf capacity %s needs larger node tables than allocated",
                     std::to_string(th).c_str());
     c->th = th;
+    return MKNN_OK;
+}
+
+int mknn_get_schedule(const mknn_ctx *c, mknn_schedule *out)
+{
+    if (!c || !out) return MKNN_E_INVAL;
+    out->leaf_capacity = c->th;
+    out->max_level = c->L;
+    out->sweep = c->sweep;
+    out->group_k = c->group_k ? 1 : 0;
+    return MKNN_OK;
+}
+
+int mknn_set_schedule(mknn_ctx *c, const mknn_schedule *sc)
+{
+    if (!c || !sc) return MKNN_E_INVAL;
+    if (sc->leaf_capacity < 1) return fail(c, MKNN_E_INVAL, "leaf capacity must be >= 1%s");
+    if (sc->max_level < 1 || sc->max_level > kCodeLevels)
+        return fail(c, MKNN_E_INVAL, "max_level must be in 1..16%s");
+    if (sc->sweep != MKNN_SWEEP_AUTO && sc->sweep != MKNN_SWEEP_LANE &&
+        sc->sweep != MKNN_SWEEP_WAVE)
+        return fail(c, MKNN_E_INVAL, "unknown sweep flavour%s");
+    if (node_capacity(c->cfg.n_max, sc->leaf_capacity, sc->max_level) > c->ix.node_cap)
+        return fail(c, MKNN_E_CAPACITY, "schedule needs larger node tables than allocated%s");
+    c->th = sc->leaf_capacity;
+    c->L = sc->max_level;
+    c->sweep = sc->sweep;
+    c->group_k = sc->group_k != 0;
     return MKNN_OK;
 }
 

@@ -80,6 +80,10 @@ struct PointPrep {
 };
 
 int k_class(int k);
+// List size (64, 128, 256, 512 or 1024 keys) of the one-query-per-wavefront
+// kernel for a largest k.
+int k_class_wave(int k);
+void launch_knn_wave(const QueryArgs &qa, int kclass, hipStream_t s);
 void launch_point_prep(const PointPrep &p, hipStream_t s);
 void launch_point_place(const uint32_t *codes, const uint32_t *rows, uint32_t nq, const float *qx,
                         const float *qy, const int32_t *exclude, const Point *pts, uint32_t n,

@@ -64,7 +64,7 @@ def test_traffic_needs_the_same_maximum_level():
 
 def test_digest_ignores_comments_not_code():
     here = {f: open(os.path.join(ROOT, "paper_1412_6170_amd", "csrc", f)).read()
-            for f in ("query.hip", "query.hpp", "mknn_internal.hpp")}
+            for f in bench.DIGEST_FILES}
     base = bench.query_source_digest(here.get)
     commented = dict(here)
     commented["query.hip"] = "// a new comment\n/* and a block\n comment */\n" + here["query.hip"]

@@ -86,7 +86,8 @@ def test_footprint_is_host_only_and_monotone():
 
 def test_footprint_at_the_largest_sizes():
     """n_max up to 2^31 - 1 and k_max = 128: sizes are 64-bit and grow
-    linearly (no overflow); one past the limit is rejected."""
+    linearly (no overflow); one past the limits is rejected (n_max, and k_max
+    above MKNN_K_LIMIT = 1024)."""
     top = 2 ** 31 - 1
     a = binding.footprint(n_max=top // 2, q_max=top // 2, k_max=128, leaf_capacity=64)
     b = binding.footprint(n_max=top, q_max=top, k_max=128, leaf_capacity=64)
@@ -95,7 +96,8 @@ def test_footprint_at_the_largest_sizes():
     with pytest.raises(binding.MknnError):
         binding.footprint(n_max=2 ** 31, k_max=8)
     with pytest.raises(binding.MknnError):
-        binding.footprint(n_max=1000, k_max=129)
+        binding.footprint(n_max=1000, k_max=1025)
+    assert binding.footprint(n_max=1000, k_max=1024) > binding.footprint(n_max=1000, k_max=128)
 
 
 def test_readme_c_example_compiles(tmp_path):

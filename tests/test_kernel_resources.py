@@ -30,7 +30,7 @@ def kernel_descriptors(src, tmp_path):
     return kds
 
 
-@pytest.mark.parametrize("name", ["index.hip", "query.hip"])
+@pytest.mark.parametrize("name", ["index.hip", "query.hip", "query_wave.hip"])
 def test_no_scratch(name, tmp_path):
     kds = kernel_descriptors(os.path.join(build.HERE, "csrc", name), tmp_path)
     assert kds, "no kernels found"
