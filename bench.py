@@ -254,10 +254,12 @@ def copy_calibration():
                       "repeats": 5}), flush=True)
 
 
-def serving_bench(args):
+def run_serving(args):
     """Many independent scenes served with continuous batching: scene sizes
     log-uniform in [10k, 2M] objects, k in {8, 32}, tick requests arriving as
-    a Poisson process; latency from arrival to device completion."""
+    a Poisson process; latency from arrival to device completion.  Returns
+    the summary (saturation rate, then the Poisson run at 0.7 x that rate
+    unless args.rate is set)."""
     import torch
     from paper_1412_6170_amd import serving, workloads
     torch.cuda.set_device(0)
@@ -277,11 +279,12 @@ def serving_bench(args):
     budget = int(args.hbm_budget_gib * 2 ** 30)
     srv = serving.Server(scenes, hbm_budget=budget, slots=args.slots)
     ids = [s.sid for s in scenes]
+    by_id = {s.sid: s for s in scenes}
     # warm-up: one tick of every scene (contexts created, kernels loaded)
     srv.run([(0.0, sid, 0) for sid in ids])
     # Saturation: every request of the schedule present at once.
     sat_done = srv.run([(0.0, sid, t) for sid in ids for t in range(args.scene_ticks)])
-    sat = serving.summarize(sat_done, {s.sid: s for s in scenes})
+    sat = serving.summarize(sat_done, by_id)
     sat_rate = sat["requests"] / sat["makespan_s"]
     rate = args.rate if args.rate > 0 else 0.7 * sat_rate
     arrivals = serving.poisson_arrivals(ids, args.scene_ticks, rate=rate,
@@ -289,23 +292,47 @@ def serving_bench(args):
     print("bench: saturation %.0f requests/s; serving %d requests at %.0f/s" % (
         sat_rate, len(arrivals), rate), file=sys.stderr, flush=True)
     done = srv.run(arrivals)
-    summ = serving.summarize(done, {s.sid: s for s in scenes})
-    out = {"metric": "served k-NN queries/s and tick latency, many scenes, continuous batching",
-           "value": summ["queries_per_s"], "unit": "queries/s", "n_gpus": 1,
-           "higher_is_better": True, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": "serving_mix", "scenes": args.scenes,
-                      "objects_total": int(sum(s.n for s in scenes)),
-                      "ticks_per_scene": args.scene_ticks, "rate_per_s": rate,
-                      "saturation_requests_per_s": sat_rate,
-                      "saturation_queries_per_s": sat["queries_per_s"],
-                      "slots": args.slots, "hbm_budget_gib": args.hbm_budget_gib,
-                      "description": "scene sizes log-uniform in [1e4, 2e6], k in {8, 32}, "
-                                     "clustered moving objects, Poisson tick requests at 0.7 x "
-                                     "the saturation rate unless --rate is given"},
+    summ = serving.summarize(done, by_id)
+    # Algorithmic bytes of the served ticks (as tick_bytes), over the span.
+    served_bytes = sum(tick_bytes(r.scene.n, r.scene.n, r.scene.n * r.scene.k, False)
+                       for r in done)
+    out = {"queries_per_s": summ["queries_per_s"], "unit": "queries/s",
            "p50_latency_ms": summ["p50_latency_ms"], "p99_latency_ms": summ["p99_latency_ms"],
            "requests": summ["requests"], "makespan_s": summ["makespan_s"],
-           "admissions": srv.admissions, "evictions": srv.evictions}
+           "rate_per_s": rate, "saturation_requests_per_s": sat_rate,
+           "saturation_queries_per_s": sat["queries_per_s"],
+           "tick_hbm_frac": served_bytes / summ["makespan_s"] / 1e9 / HBM_PEAK_GBS,
+           "scenes": args.scenes, "objects_total": int(sum(s.n for s in scenes)),
+           "ticks_per_scene": args.scene_ticks, "slots": args.slots,
+           "hbm_budget_gib": args.hbm_budget_gib,
+           "admissions": srv.admissions, "evictions": srv.evictions,
+           "description": "scene sizes log-uniform in [1e4, 2e6], k in {8, 32}, clustered "
+                          "moving objects, Poisson tick requests at 0.7 x the saturation rate "
+                          "unless a rate is given; latency from arrival to device completion"}
     srv.close()
+    del scenes
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return out
+
+
+def serving_bench(args):
+    """The serving workload alone, printed as its own JSON line."""
+    r = run_serving(args)
+    out = {"metric": "served k-NN queries/s and tick latency, many scenes, continuous batching",
+           "value": r["queries_per_s"], "unit": "queries/s", "n_gpus": 1,
+           "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "serving_mix", "scenes": r["scenes"],
+                      "objects_total": r["objects_total"],
+                      "ticks_per_scene": r["ticks_per_scene"], "rate_per_s": r["rate_per_s"],
+                      "saturation_requests_per_s": r["saturation_requests_per_s"],
+                      "saturation_queries_per_s": r["saturation_queries_per_s"],
+                      "slots": r["slots"], "hbm_budget_gib": r["hbm_budget_gib"],
+                      "description": r["description"]},
+           "p50_latency_ms": r["p50_latency_ms"], "p99_latency_ms": r["p99_latency_ms"],
+           "requests": r["requests"], "makespan_s": r["makespan_s"],
+           "tick_hbm_frac": r["tick_hbm_frac"],
+           "admissions": r["admissions"], "evictions": r["evictions"]}
     print(json.dumps(out), flush=True)
 
 
@@ -416,6 +443,8 @@ def main():
     ap.add_argument("--slots", type=int, default=4, help="ticks in flight at most")
     ap.add_argument("--hbm-budget-gib", type=float, default=64.0)
     ap.add_argument("--serving-seed", type=int, default=7)
+    ap.add_argument("--no-serving", dest="serving_leg", action="store_false", default=True,
+                    help="skip the serving leg of the default line")
     args = ap.parse_args()
 
     if args.copy_calibration:
@@ -636,6 +665,11 @@ def main():
                         "rebuilds": pol.rebuilds, "refits": pol.refits,
                         "factor": args.reuse_factor}
         rctx.close()
+
+    if args.serving_leg and args.workload == "clustered_1m":
+        # The served form of the same path: many scenes (up to 2M objects,
+        # k in {8, 32}) under continuous batching.
+        out["serving"] = run_serving(args)
 
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle", file=sys.stderr, flush=True)

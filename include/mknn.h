@@ -184,7 +184,10 @@ MKNN_API int mknn_destroy(mknn_ctx *ctx);
  * has passed the next mknn_advance_tick.
  * Host input is validated during the call (MKNN_E_RANGE leaves the previous
  * snapshot in place).  Device input is validated on the device; a bad value
- * makes the next mknn_sync / mknn_fetch return MKNN_E_RANGE.
+ * makes the next mknn_sync / mknn_fetch return MKNN_E_RANGE.  Errors found
+ * on the device (here and in the other calls) are kept until a
+ * synchronising call reports them, whichever launch -- eager or replayed
+ * from a captured graph -- found them.
  * Errors: MKNN_E_INVAL, MKNN_E_CAPACITY (n > n_max), MKNN_E_RANGE.
  * After a load, mknn_advance_tick must run before the next query.
  */
@@ -357,6 +360,14 @@ MKNN_API int mknn_get_schedule(const mknn_ctx *ctx, mknn_schedule *out);
  * MKNN_E_CAPACITY.  On error nothing changes.
  */
 MKNN_API int mknn_set_schedule(mknn_ctx *ctx, const mknn_schedule *s);
+
+/*
+ * mknn_set_epochs -- testing hook: the tags the next index step and query
+ * will be one past (build_epoch, query_epoch), both in 1 .. 2^24-1.  Tags
+ * wrap from 2^24-1 to 1; this lets a test cross the wrap without running
+ * 2^24 ticks.  Results never depend on the tags.  Errors: MKNN_E_INVAL.
+ */
+MKNN_API int mknn_set_epochs(mknn_ctx *ctx, uint32_t build_epoch, uint32_t query_epoch);
 
 /* mknn_reset_timing -- forget the device times and counters recorded so far
  * (the means and totals in mknn_stats restart). */

@@ -100,6 +100,7 @@ def lib():
             "mknn_default_leaf_capacity": ([_i32], _i32),
             "mknn_footprint": ([ctypes.POINTER(Config), ctypes.POINTER(_i64)], _i32),
             "mknn_get_schedule": ([_vp, ctypes.POINTER(Schedule)], _i32),
+            "mknn_set_epochs": ([_vp, ctypes.c_uint32, ctypes.c_uint32], _i32),
             "mknn_set_schedule": ([_vp, ctypes.POINTER(Schedule)], _i32),
         }
         for name, (args, res) in sig.items():
@@ -432,6 +433,11 @@ class Context:
             return None
         self._check(rc)
         return ms.value
+
+    def set_epochs(self, build_epoch, query_epoch):
+        """Testing hook: the next index step and query take the tags one
+        past these (tags wrap from 2^24 - 1 to 1)."""
+        self._check(lib().mknn_set_epochs(self._h, int(build_epoch), int(query_epoch)))
 
     def set_leaf_capacity(self, th):
         self._check(lib().mknn_set_leaf_capacity(self._h, int(th)))

@@ -178,27 +178,47 @@ int read_counters(mknn_ctx *c, IndexCounters *h)
     return MKNN_OK;
 }
 
+// Error words are sticky: a kernel that meets bad input raises its word to
+// a nonzero value, and the word keeps it -- whichever launch, eager or
+// replayed from a graph, raised it -- until the host has read and reported
+// it here; then every error word is cleared (by a kernel, so that nothing
+// here records a memset) and the first error found is returned.
+__global__ void k_clear_flags(IndexCounters *ctr)
+{
+    ctr->bad_coord = 0;
+    ctr->bad_nodes = 0;
+    ctr->bad_issuer = 0;
+    ctr->bad_k = 0;
+    ctr->bad_sync_build = 0;
+    ctr->bad_sync_query = 0;
+    ctr->bad_centre = 0;
+}
+
 int check_deferred(mknn_ctx *c)
 {
     if (!c->ticked) return MKNN_OK;
     IndexCounters h{};
     int rc = read_counters(c, &h);
     if (rc) return rc;
-    if (h.bad_coord == c->build_epoch)
-        return fail(c, MKNN_E_RANGE, "a device coordinate is not finite or outside [0,1)%s");
-    if (h.bad_nodes == c->build_epoch)
-        return fail(c, MKNN_E_DEVICE, "node table capacity exceeded%s");
-    if (h.bad_sync_build == c->build_epoch)
-        return fail(c, MKNN_E_DEVICE, "index build: a look-back wait gave up%s");
-    if (c->queried && h.bad_sync_query == c->query_epoch)
+    if (!(h.bad_coord | h.bad_nodes | h.bad_sync_build | h.bad_sync_query | h.bad_issuer |
+          h.bad_k | h.bad_centre))
+        return MKNN_OK;
+    k_clear_flags<<<1, 1, 0, c->stream>>>(c->ix.ctr);
+    rc = check_launch(c, "clear error words");
+    if (!rc) {
+        const hipError_t e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) rc = hip_fail(c, e, "hipStreamSynchronize");
+    }
+    if (rc) return rc;
+    if (h.bad_nodes) return fail(c, MKNN_E_DEVICE, "node table capacity exceeded%s");
+    if (h.bad_sync_build) return fail(c, MKNN_E_DEVICE, "index build: a look-back wait gave up%s");
+    if (h.bad_sync_query)
         return fail(c, MKNN_E_DEVICE, "query indexing: a look-back wait gave up%s");
-    if (c->queried && h.bad_issuer == c->query_epoch)
-        return fail(c, MKNN_E_INVAL, "a device issuer is outside [0,n)%s");
-    if (c->queried && h.bad_k == c->query_epoch)
-        return fail(c, MKNN_E_INVAL, "a device k is outside [1,k_max]%s");
-    if (c->queried && h.bad_centre == c->query_epoch)
-        return fail(c, MKNN_E_RANGE, "a device query centre is not finite or outside [0,1)%s");
-    return MKNN_OK;
+    if (h.bad_coord)
+        return fail(c, MKNN_E_RANGE, "a device coordinate is not finite or outside [0,1)%s");
+    if (h.bad_issuer) return fail(c, MKNN_E_INVAL, "a device issuer is outside [0,n)%s");
+    if (h.bad_k) return fail(c, MKNN_E_INVAL, "a device k is outside [1,k_max]%s");
+    return fail(c, MKNN_E_RANGE, "a device query centre is not finite or outside [0,1)%s");
 }
 
 bool valid_where(int32_t w) { return w == MKNN_HOST || w == MKNN_DEVICE; }
@@ -985,6 +1005,17 @@ int mknn_set_schedule(mknn_ctx *c, const mknn_schedule *sc)
     c->L = sc->max_level;
     c->sweep = sc->sweep;
     c->group_k = sc->group_k != 0;
+    return MKNN_OK;
+}
+
+int mknn_set_epochs(mknn_ctx *c, uint32_t build_epoch, uint32_t query_epoch)
+{
+    if (!c) return MKNN_E_INVAL;
+    if (build_epoch < 1 || build_epoch >= (1u << 24) || query_epoch < 1 ||
+        query_epoch >= (1u << 24))
+        return fail(c, MKNN_E_INVAL, "epochs run 1 .. 2^24-1%s");
+    c->build_epoch = build_epoch;
+    c->query_epoch = query_epoch;
     return MKNN_OK;
 }
 

@@ -321,6 +321,9 @@ __global__ void k_morton(const float *__restrict__ x, const float *__restrict__ 
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     // The build's scan and sort workspace starts at zero.
     for (int64_t w = i; w < ws_words; w += (int64_t)gridDim.x * blockDim.x) ws[w] = 0ull;
+    // This build's deepest-level word starts at its own epoch (raised by
+    // k_leaf_nodes, which runs after this kernel).
+    if (i == 0) ctr->deepest = epoch << 8;
     if (i >= n) return;
     float px = x[i], py = y[i];
     // NaN fails both comparisons; -0.0 passes.
@@ -1021,10 +1024,18 @@ __global__ void k_refit(const float *__restrict__ x, const float *__restrict__ y
     }
 }
 
+// The drift word starts at this refit's epoch with a zero displacement, by
+// a plain store ahead of k_refit's maxima.
+__global__ void k_drift_start(IndexCounters *ctr, uint32_t epoch)
+{
+    ctr->drift = (unsigned long long)epoch << 32;
+}
+
 void launch_refit(IndexBuffers &b, const float *x, const float *y, int64_t n, uint32_t epoch,
                   hipStream_t s)
 {
     if (n <= 0) return;
+    k_drift_start<<<1, 1, 0, s>>>(b.ctr, epoch);
     const int T = 256;
     const int64_t g = (n + T - 1) / T;
     k_refit<<<(uint32_t)(g < 1024 ? g : 1024), T, 0, s>>>(x, y, (uint32_t)n, b.pts, b.anchor, b.ctr,

@@ -45,21 +45,25 @@ struct __align__(16) Node {
 };
 
 // Device scalars written by the build and read by later kernels (no host
-// round trip between the build and the queries).  Flags and the deepest
-// level are tagged with the build's (or query's) epoch in their high bits
-// and raised with atomicMax, so nothing has to clear them between ticks:
-// a value from an older epoch is simply smaller.
+// round trip between the build and the queries).  The error words are
+// sticky: a kernel that meets bad input raises its word to its (nonzero)
+// epoch with atomicMax, and the word stays nonzero until the host reads
+// and clears it.  The deepest level and the drift are tagged with the
+// build's epoch in their high bits; each build (refit) first stores its
+// own epoch with a plain store, then raises the value with atomicMax, so a
+// larger value from another epoch (after the epochs wrap, or from a graph
+// replayed out of order) never shadows it.
 struct IndexCounters {
     uint32_t n_leaves;
     uint32_t n_nodes;
     uint32_t deepest;        // (build epoch << 8) | deepest leaf level
-    uint32_t bad_coord;      // build epoch in which a coordinate was outside [0,1)
-    uint32_t bad_nodes;      // build epoch in which the node tables overflowed
-    uint32_t bad_issuer;     // query epoch in which an issuer was outside [0,n)
-    uint32_t bad_k;          // query epoch in which a k was outside [1,k_max]
-    uint32_t bad_sync_build; // build epoch in which a look-back wait gave up
-    uint32_t bad_sync_query; // query epoch in which a look-back wait gave up
-    uint32_t bad_centre;     // query epoch in which a free centre was outside [0,1)
+    uint32_t bad_coord;      // nonzero: a coordinate was outside [0,1)
+    uint32_t bad_nodes;      // nonzero: the node tables overflowed
+    uint32_t bad_issuer;     // nonzero: an issuer was outside [0,n)
+    uint32_t bad_k;          // nonzero: a k was outside [1,k_max]
+    uint32_t bad_sync_build; // nonzero: a build look-back wait gave up
+    uint32_t bad_sync_query; // nonzero: a query look-back wait gave up
+    uint32_t bad_centre;     // nonzero: a free centre was outside [0,1)
     uint32_t pad;
     // (build epoch << 32) | fp32 bits of the largest per-axis displacement of
     // any object since the last full build, raised by each refit tick.

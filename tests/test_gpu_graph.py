@@ -95,3 +95,43 @@ def test_leaf_capacity_switch_between_ticks():
         with pytest.raises(binding.MknnError) as e:
             c.set_leaf_capacity(0)
         assert e.value.code == -1
+
+
+def test_replayed_graph_reports_bad_device_coordinate():
+    """A bad device coordinate seen by a replayed graph is reported at the
+    next synchronisation even after later eager ticks, and once reported the
+    context carries on."""
+    w = workloads.clustered_1m(n=20_000, ticks=1)
+    x, y, _, _, _ = w.tick(0)
+    k = 8
+    exp = oracle.brute_knn(x, y, k=k, threads=16)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        dx, dy = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+        c = binding.Context(w.n, w.n, k, leaf_capacity=16, stream=s.cuda_stream)
+        c.load_positions(dx, dy)
+        c.advance_tick()
+        c.query(k=k)
+        c.sync()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            c.load_positions(dx, dy)
+            c.advance_tick()
+            c.query(k=k)
+        # eager ticks after the capture move the context's tags on
+        for _ in range(2):
+            c.load_positions(x, y)
+            c.advance_tick()
+            c.query(k=k)
+        c.sync()
+        dx[5] = 2.0
+        g.replay()
+        with pytest.raises(binding.MknnError) as e:
+            c.sync()
+        assert e.value.code == -2
+        dx[5] = float(x[5])
+        g.replay()
+        ids, d2, cnt, _ = c.fetch()
+        assert np.array_equal(ids, exp[0]) and np.array_equal(bits(d2), bits(exp[1]))
+        del g
+        c.close()

@@ -118,3 +118,68 @@ def test_reuse_policy_stays_exact():
             check(c.fetch(), oracle.knn(x, y, k=16, th=16, threads=16))
     say("policy ticks:", kinds)
     assert kinds[0] == "build" and "refit" in kinds
+
+
+def jittered(x0, y0, rng, amp):
+    x = f32(np.clip(x0 + rng.uniform(-amp, amp, len(x0)), 0, 1 - 2 ** -24))
+    y = f32(np.clip(y0 + rng.uniform(-amp, amp, len(y0)), 0, 1 - 2 ** -24))
+    return x, y
+
+
+def test_refit_across_epoch_wrap():
+    """Refit ticks whose tags cross the wrap from 2^24 - 1 to 1: the drift of
+    each refit must be the one its queries use (a refit that lost its drift
+    to a larger word of an earlier epoch would prune with unpadded boxes)."""
+    x0, y0 = family("clustered", 20_000, 71)
+    rng = np.random.default_rng(72)
+    k = 16
+    with binding.Context(len(x0), len(x0), k, leaf_capacity=16) as c:
+        c.set_epochs(2 ** 24 - 3, 2 ** 24 - 2)
+        c.load_positions(x0, y0)
+        c.advance_tick()
+        for step in range(5):
+            x, y = jittered(x0, y0, rng, 3e-3 * (5 - step))
+            say("refit across the epoch wrap, step %d" % step)
+            c.load_positions(x, y)
+            c.refit_tick()
+            c.query(k=k)
+            check(c.fetch(), oracle.brute_knn(x, y, k=k, threads=16))
+            assert c.stats()["drift"] > 0
+
+
+def test_refit_graphs_replayed_out_of_order():
+    """Refit ticks captured as graphs and replayed in another order than
+    captured, with eager ticks between: every replay is exact."""
+    x0, y0 = family("clustered", 30_000, 73)
+    rng = np.random.default_rng(74)
+    k = 12
+    pos = [jittered(x0, y0, rng, amp) for amp in (4e-3, 1e-3, 2e-3)]
+    exp = [oracle.brute_knn(x, y, k=k, threads=16) for x, y in pos]
+    dev = [(torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()) for x, y in pos]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        c = binding.Context(len(x0), len(x0), k, leaf_capacity=16, stream=s.cuda_stream)
+        d0 = (torch.from_numpy(x0).cuda(), torch.from_numpy(y0).cuda())
+        c.load_positions(*d0)
+        c.advance_tick()
+        c.query(k=k)
+        c.sync()
+        graphs = []
+        for t in range(len(pos)):
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=s):
+                c.load_positions(*dev[t])
+                c.refit_tick()
+                c.query(k=k)
+            graphs.append(g)
+        for t in (2, 0, 1, 2, 1, 0):
+            say("replay refit graph %d" % t)
+            graphs[t].replay()
+            check(c.fetch(), exp[t])
+            # An eager refit tick between replays (later tags than every graph).
+            c.load_positions(*dev[(t + 1) % len(pos)])
+            c.refit_tick()
+            c.query(k=k)
+            check(c.fetch(), exp[(t + 1) % len(pos)])
+        del graphs
+        c.close()
