@@ -397,6 +397,53 @@ MKNN_API const char *mknn_status_str(int status);
 /* mknn_default_leaf_capacity -- the automatic leaf capacity for a given k. */
 MKNN_API int32_t mknn_default_leaf_capacity(int32_t k);
 
+/* Largest object count and scratch size of mknn_knn_noalloc. */
+#define MKNN_NOALLOC_MAX_N 65536
+#define MKNN_NOALLOC_SCRATCH_BYTES (16 << 20)
+
+/*
+ * mknn_knn_noalloc -- one whole tick without allocating: the index build of
+ * mknn_advance_tick and the query of mknn_query with every object querying
+ * (issuers NULL, uniform k), in one call that calls no hipMalloc, hipFree or
+ * other allocating routine.  For callers that cannot allocate device
+ * memory: code being captured into a HIP graph, tight serving loops, hosts
+ * that forbid allocation after start-up.
+ *
+ * x, y      device, n fp32 coordinates each, object id = index (as
+ *           mknn_load_positions with MKNN_DEVICE); read in place.
+ * n         0 .. MKNN_NOALLOC_MAX_N.
+ * k         1 .. MKNN_K_LIMIT; lists of up to 128 keys run one query per
+ *           lane, larger ones one query per wavefront (as mknn_query).
+ * leaf_capacity  0 = mknn_default_leaf_capacity(k); the maximum level is 16.
+ * ids, d2   device, n * k entries each: row i (object i's query, object i
+ *           excluded) is the dense row mknn_fetch returns for uniform k.
+ * counts    device, n entries: min(k, n - 1).
+ * status    device, one int32, or NULL: set to 0 when the tick's device
+ *           checks pass, else MKNN_E_RANGE (a coordinate not finite or
+ *           outside [0,1)) or MKNN_E_DEVICE (a look-back wait gave up or a
+ *           node table overflowed); the rows are then unspecified.
+ * stream    hipStream_t the work is enqueued on (NULL: the null stream).
+ *
+ * Every intermediate buffer (sort buffers, leaves, node tables, look-back
+ * words, counters) is carved from one device array of
+ * MKNN_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs on
+ * until the process ends; its address is looked up once per device on the
+ * first call there (the device current at the call).  The call only
+ * enqueues work and returns; nothing is read back.  Every call on one GPU
+ * shares that GPU's array: calls whose work overlaps on one GPU (on
+ * different streams, or from different host threads) race and give wrong
+ * rows.  Each call clears what must start at zero itself.
+ *
+ * Errors: MKNN_E_INVAL (NULL pointer with n > 0, n < 0, k outside
+ * [1, MKNN_K_LIMIT], leaf_capacity < 0), MKNN_E_CAPACITY (n above
+ * MKNN_NOALLOC_MAX_N, or the buffers for n and leaf_capacity do not fit the
+ * array: leaf capacities of 16 or more always fit), MKNN_E_DEVICE (a HIP
+ * error while looking up the array or launching).
+ */
+MKNN_API int mknn_knn_noalloc(const float *x, const float *y, int64_t n, int32_t k,
+                              int32_t leaf_capacity, int32_t *ids, float *d2, int32_t *counts,
+                              int32_t *status, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

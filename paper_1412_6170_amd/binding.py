@@ -102,6 +102,7 @@ def lib():
             "mknn_get_schedule": ([_vp, ctypes.POINTER(Schedule)], _i32),
             "mknn_set_epochs": ([_vp, ctypes.c_uint32, ctypes.c_uint32], _i32),
             "mknn_set_schedule": ([_vp, ctypes.POINTER(Schedule)], _i32),
+            "mknn_knn_noalloc": ([_vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp, _vp, _vp], _i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -135,6 +136,41 @@ def _hip():
 # hipEventDisableTiming | hipEventDisableSystemFence: an ordering-only event
 # between two streams of one device needs no system-scope release.
 _ORDER_EVENT_FLAGS = 0x2 | 0x20000000
+
+
+NOALLOC_MAX_N = 65536
+
+
+def knn_noalloc(x, y, k, ids, d2, counts, status=None, leaf_capacity=0, stream=None):
+    """mknn_knn_noalloc: one tick (index build, every object querying with
+    uniform k) that allocates nothing, writing into the caller's device
+    buffers.  x, y: float32 cuda tensors of n coordinates; ids (int32),
+    d2 (float32): n * k entries; counts (int32): n entries; status: one
+    int32 entry or None.  Runs on `stream` (a torch stream or a raw handle;
+    None: torch's current stream).  Raises MknnError on a host-checked
+    error; device-detected errors land in status."""
+    import torch
+    n = int(x.numel())
+    for t, dt, cnt in ((x, torch.float32, n), (y, torch.float32, n), (ids, torch.int32, n * k),
+                       (d2, torch.float32, n * k), (counts, torch.int32, n)):
+        if not t.is_cuda or t.dtype != dt or not t.is_contiguous() or t.numel() < cnt:
+            raise MknnError(-1, "knn_noalloc: bad buffer")
+    if status is not None and (not status.is_cuda or status.dtype != torch.int32):
+        raise MknnError(-1, "knn_noalloc: bad status buffer")
+    if stream is None:
+        handle = torch.cuda.current_stream(x.device).cuda_stream
+    elif isinstance(stream, torch.cuda.Stream):
+        handle = stream.cuda_stream
+    else:
+        handle = int(stream)
+    with torch.cuda.device(x.device):
+        rc = lib().mknn_knn_noalloc(_vp(x.data_ptr()), _vp(y.data_ptr()), n, int(k),
+                                    int(leaf_capacity), _vp(ids.data_ptr()),
+                                    _vp(d2.data_ptr()), _vp(counts.data_ptr()),
+                                    _vp(status.data_ptr()) if status is not None else None,
+                                    _vp(handle) if handle else None)
+    if rc != 0:
+        raise MknnError(rc, "mknn_knn_noalloc failed")
 
 
 def default_leaf_capacity(k):

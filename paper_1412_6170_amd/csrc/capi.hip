@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1130,3 +1131,153 @@ int mknn_get_stats(const mknn_ctx *cc, mknn_stats *out)
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// One tick without allocating (mknn_knn_noalloc): the index build and the
+// all-objects query of the context path, with every intermediate buffer
+// carved from one file-scope device array.
+// ---------------------------------------------------------------------------
+namespace {
+
+// The array every mknn_knn_noalloc call on a GPU carves its buffers from.
+// Each GPU holds its own copy at its own address.  In host code this name is
+// a host-side stand-in, not a device address: host code uses only the
+// address looked up per device below (kernel arguments, carving).
+static __device__ __align__(256) unsigned char scratch[MKNN_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kScratchDevices = 64;
+std::mutex scratch_mu;
+unsigned char *scratch_dev[kScratchDevices];  // device address per device, or null
+
+// Device address of `scratch` on device `dev`, which must be current: looked
+// up on the first call on that device and kept.
+hipError_t scratch_address(int dev, unsigned char **out)
+{
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_dev[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        scratch_dev[dev] = (unsigned char *)p;
+    }
+    *out = scratch_dev[dev];
+    return hipSuccess;
+}
+
+// Consecutive 256-byte aligned pieces of the array; ok turns false when a
+// piece does not fit.
+struct ScratchCarve {
+    unsigned char *base;
+    size_t used = 0;
+    bool ok = true;
+
+    template <class T>
+    T *take(int64_t count)
+    {
+        if (count < 1) count = 1;
+        const size_t at = (used + 255) / 256 * 256;
+        const size_t bytes = (size_t)count * sizeof(T);
+        if (!ok || at + bytes > (size_t)MKNN_NOALLOC_SCRATCH_BYTES) {
+            ok = false;
+            return nullptr;
+        }
+        used = at + bytes;
+        return (T *)(base + at);
+    }
+};
+
+__global__ void k_noalloc_status(const IndexCounters *ctr, int32_t *status)
+{
+    const bool device_err = (ctr->bad_nodes | ctr->bad_sync_build) != 0;
+    *status = ctr->bad_coord ? MKNN_E_RANGE : device_err ? MKNN_E_DEVICE : MKNN_OK;
+}
+
+__global__ void k_noalloc_ok(int32_t *status) { *status = MKNN_OK; }
+
+}  // namespace
+
+extern "C" int mknn_knn_noalloc(const float *x, const float *y, int64_t n, int32_t k,
+                                int32_t leaf_capacity, int32_t *ids, float *d2, int32_t *counts,
+                                int32_t *status, void *stream)
+{
+    if (n < 0 || k < 1 || k > MKNN_K_LIMIT || leaf_capacity < 0) return MKNN_E_INVAL;
+    if (n > 0 && (!x || !y || !ids || !d2 || !counts)) return MKNN_E_INVAL;
+    if (n > MKNN_NOALLOC_MAX_N) return MKNN_E_CAPACITY;
+    hipStream_t s = (hipStream_t)stream;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kScratchDevices) {
+        (void)hipGetLastError();
+        return MKNN_E_DEVICE;
+    }
+    unsigned char *base = nullptr;
+    if (scratch_address(dev, &base) != hipSuccess) {
+        (void)hipGetLastError();
+        return MKNN_E_DEVICE;
+    }
+    if (n == 0) {
+        if (status) k_noalloc_ok<<<1, 1, 0, s>>>(status);
+        return hipGetLastError() == hipSuccess ? MKNN_OK : MKNN_E_DEVICE;
+    }
+    const int th = leaf_capacity ? leaf_capacity : mknn_default_leaf_capacity(k);
+    const int L = kCodeLevels;
+
+    // The buffers of one context's index, sized for this call's n.
+    IndexBuffers ix{};
+    ix.n_cap = n;
+    ix.node_cap = node_capacity(n, th, L);
+    ix.ws.cap_words = workspace_words(n);
+    ScratchCarve cv{base};
+    for (int i = 0; i < 2; ++i) {
+        ix.sort.keys[i] = cv.take<uint32_t>(n);
+        ix.sort.vals[i] = cv.take<uint32_t>(n);
+    }
+    ix.ws.base = cv.take<uint64_t>(ix.ws.cap_words);
+    ix.xy = cv.take<float2>(n);
+    ix.anchor = cv.take<float2>(n);
+    ix.pts = cv.take<Point>(n);
+    ix.inv = nullptr;  // only subset queries use it
+    ix.leaf_of = cv.take<int32_t>(n);
+    ix.leaf_begin = cv.take<int32_t>(n);
+    ix.leaf_end = cv.take<int32_t>(n);
+    ix.leaf_level = cv.take<int32_t>(n);
+    ix.leaf_code = cv.take<uint32_t>(n);
+    ix.cnt_f = cv.take<uint32_t>(n);
+    ix.cnt_r = cv.take<uint32_t>(n);
+    ix.leaf_node_f = cv.take<int32_t>(n);
+    ix.leaf_node_r = cv.take<int32_t>(n);
+    ix.fwd = cv.take<Node>(ix.node_cap);
+    ix.rev = cv.take<Node>(ix.node_cap);
+    ix.ctr = cv.take<IndexCounters>(1);
+    if (!cv.ok) return MKNN_E_CAPACITY;
+
+    // The counters and error words start at zero (the build's first kernel
+    // zeroes its own look-back words); epoch 1 tags this build.
+    const uint32_t epoch = 1;
+    k_reset_counters<<<1, 1, 0, s>>>(ix.ctr);
+    launch_build_index(ix, x, y, n, th, L, epoch, s);
+
+    QueryArgs qa{};
+    qa.pts = ix.pts;
+    qa.n = (uint32_t)n;
+    qa.fwd = ix.fwd;
+    qa.rev = ix.rev;
+    qa.leaf_of = ix.leaf_of;
+    qa.leaf_begin = ix.leaf_begin;
+    qa.leaf_end = ix.leaf_end;
+    qa.leaf_node_f = ix.leaf_node_f;
+    qa.leaf_node_r = ix.leaf_node_r;
+    qa.ctr = ix.ctr;
+    qa.node_cap = (int32_t)ix.node_cap;
+    qa.nq = (uint32_t)n;
+    qa.k_uniform = k;
+    qa.out_ids = ids;
+    qa.out_d2 = d2;
+    qa.out_cnt = counts;
+    qa.build_epoch = epoch;
+    qa.pos_mask = 0xffffffffu;
+    if (k > 128) launch_knn_wave(qa, k_class_wave(k), s);
+    else launch_knn(qa, k_class(k), s);
+    if (status) k_noalloc_status<<<1, 1, 0, s>>>(ix.ctr, status);
+    return hipGetLastError() == hipSuccess ? MKNN_OK : MKNN_E_DEVICE;
+}
