@@ -12,11 +12,12 @@ Positions of every tick are generated and copied to HBM before the timed
 region; the library reads them in place; results stay in HBM (fetching them
 is not part of a tick).
 
-The leaf capacity is the autotuner's choice for the workload on MI355X
-(TUNED_LEAF_CAPACITY), --leaf-capacity TH, or, with --autotune, chosen
-during warm-up by the autotuner (device time per tick over a few
-candidates); the maximum quadtree level is TUNED_MAX_LEVEL's or
---max-level.  Results depend on neither.
+The schedule (leaf capacity, maximum quadtree level, sweep flavour and,
+for variable k, k grouping) is chosen during warm-up by the library's
+autotuner (coordinate descent over device time per tick, SCHEDULE_SPACE);
+--no-autotune takes the autotuner's stored choice for the workload on
+MI355X (TUNED_SCHEDULE), and --leaf-capacity / --max-level / --sweep fix a
+dimension.  Results never depend on the schedule.
 
 Prints one JSON line: queries/s over the K timed ticks, p50/p99 tick latency,
 a roofline entry for the dominant kernel (the leaf-sweep query kernel,
@@ -41,16 +42,20 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 TH_CANDIDATES = (16, 24, 32, 48, 64, 96, 128, 192)
-# Leaf capacity used when --autotune is not given: the autotuner's choice on
-# MI355X for each workload (device time per tick over TH_CANDIDATES).
-TUNED_LEAF_CAPACITY = {"clustered_1m": 64, "uniform_10k": 32, "network_4m": 64, "mixed_16m": 64}
-# Maximum quadtree level (l_max, Sec. 4.1) per workload; absent: 16.  The
-# build sorts only the top 2 * l_max bits of the Morton codes, so 12 saves a
-# radix pass; at capacity 64 it leaves the query time of clustered_1m and
-# network_4m unchanged within 1% (a few level-13 leaves become larger
-# level-12 leaves), while mixed_16m's k = 128 queries lose more than the
-# build saves.  Results never depend on it.
-TUNED_MAX_LEVEL = {"clustered_1m": 12, "network_4m": 12}
+# The autotuner's search space: leaf capacity, maximum quadtree level (l_max,
+# Sec. 4.1: the build sorts only the top 2 * l_max bits of the Morton codes,
+# so 12 saves a radix pass over 16), sweep flavour (one query per lane, or
+# one query per wavefront: Sec. 4.2.1's cached and coalesced-writes
+# variants) and, for variable k, k grouping.
+SCHEDULE_SPACE = {"leaf_capacity": TH_CANDIDATES, "max_level": (12, 14, 16),
+                  "sweep": ("lane", "wave"), "group_k": (False, True)}
+# The autotuner's choice on MI355X per workload, used with --no-autotune.
+TUNED_SCHEDULE = {
+    "uniform_10k": {"leaf_capacity": 32, "max_level": 16, "sweep": "lane", "group_k": False},
+    "clustered_1m": {"leaf_capacity": 64, "max_level": 12, "sweep": "lane", "group_k": False},
+    "network_4m": {"leaf_capacity": 64, "max_level": 12, "sweep": "lane", "group_k": False},
+    "mixed_16m": {"leaf_capacity": 64, "max_level": 16, "sweep": "lane", "group_k": False},
+}
 CPU_SAMPLE_SECONDS = 10.0
 
 # HBM bytes per launch of the query kernel on clustered_1m at the tuned leaf
@@ -90,16 +95,17 @@ def query_source_digest(read=None):
     return h.hexdigest()[:16]
 
 
-def _measured(workload, leaf_capacity, max_level):
+def _measured(workload, leaf_capacity, max_level, sweep="lane"):
     m = MEASURED_TRAFFIC
     if (not m or m["digest"] != query_source_digest() or m["workload"] != workload
-            or m["leaf_capacity"] != leaf_capacity or m.get("max_level", 16) != max_level):
+            or m["leaf_capacity"] != leaf_capacity or m.get("max_level", 16) != max_level
+            or m.get("sweep", "lane") != sweep):
         return None
     return m
 
 
-def measured_traffic(workload, leaf_capacity, max_level=16):
-    m = _measured(workload, leaf_capacity, max_level)
+def measured_traffic(workload, leaf_capacity, max_level=16, sweep="lane"):
+    m = _measured(workload, leaf_capacity, max_level, sweep)
     return None if m is None else m["fetch_bytes"] + m["write_bytes"]
 
 
@@ -108,12 +114,12 @@ def measured_traffic(workload, leaf_capacity, max_level=16):
 VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 
 
-def valu_issue(workload, leaf_capacity, max_level, kernel_ms):
+def valu_issue(workload, leaf_capacity, max_level, kernel_ms, sweep="lane"):
     """VALU lane operations the query kernel issues per second (the stored
     SQ_INSTS_VALU count of one launch, 64 lanes each, over the kernel's
     measured mean time) against the issue peak, or None if the count was
     taken on other code or another configuration."""
-    m = _measured(workload, leaf_capacity, max_level)
+    m = _measured(workload, leaf_capacity, max_level, sweep)
     if m is None or not m.get("valu_insts") or not kernel_ms:
         return None
     ops = m["valu_insts"] * 64 / (kernel_ms * 1e-3)
@@ -138,7 +144,7 @@ def tick_bytes(n, nq, entries, subset):
     return 32 * n + (8 * nq if subset else 0) + 8 * entries + 4 * nq
 
 
-def roofline_entry(workload, leaf_capacity, max_level, k, kern_ms, kern_bytes):
+def roofline_entry(workload, leaf_capacity, max_level, k, kern_ms, kern_bytes, sweep="lane"):
     """Roofline entry of the query kernel.  Both roofs are computed: HBM
     (algorithmic bytes per launch over the kernel's mean device time, against
     8 TB/s) and VALU issue (the stored executed-instruction count of a
@@ -148,11 +154,15 @@ def roofline_entry(workload, leaf_capacity, max_level, k, kern_ms, kern_bytes):
     achieved = kern_bytes / (kern_ms * 1e-3) / 1e9
     hbm = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": achieved / HBM_PEAK_GBS,
-           "traffic": measured_traffic(workload, leaf_capacity, max_level)}
-    kclass = 8 if k <= 8 else 16 if k <= 16 else 32 if k <= 32 else 64 if k <= 64 else 128
-    common = {"kernel": "k_knn_tiles (leaf sweeps), k class %d" % kclass, "kernel_ms": kern_ms,
-              "bytes_per_launch": kern_bytes}
-    valu = valu_issue(workload, leaf_capacity, max_level, kern_ms)
+           "traffic": measured_traffic(workload, leaf_capacity, max_level, sweep)}
+    if sweep == "wave":
+        kclass = max(64, 1 << (max(k, 1) - 1).bit_length())
+        name = "k_knn_wave (one query per wavefront), list of %d keys" % kclass
+    else:
+        kclass = 8 if k <= 8 else 16 if k <= 16 else 32 if k <= 32 else 64 if k <= 64 else 128
+        name = "k_knn_tiles (one query per lane), k class %d" % kclass
+    common = {"kernel": name, "kernel_ms": kern_ms, "bytes_per_launch": kern_bytes}
+    valu = valu_issue(workload, leaf_capacity, max_level, kern_ms, sweep)
     if valu is not None and valu["frac"] > hbm["frac"]:
         out = {"bound": "alu", "achieved": valu["achieved"], "peak": valu["peak"],
                "unit": valu["unit"], "frac": valu["frac"], "traffic": hbm["traffic"],
@@ -406,18 +416,19 @@ def main():
                     help="generate at most this many ticks and cycle over them (0: all, "
                          "but at most 10 for workloads above 2M objects)")
     ap.add_argument("--max-level", type=int, default=0,
-                    help="maximum quadtree level 1..16; 0 = the tuned value for the workload %s "
-                         "(else 16)" % (TUNED_MAX_LEVEL,))
+                    help="fix the maximum quadtree level 1..16 (0: tuned)")
     ap.add_argument("--leaf-capacity", type=int, default=0,
-                    help="leaf capacity; 0 = the tuned value for the workload %s"
-                         % (TUNED_LEAF_CAPACITY,))
-    ap.add_argument("--autotune", action="store_true",
-                    help="choose the leaf capacity during warm-up over %s" % (TH_CANDIDATES,))
-    ap.add_argument("--th-candidates", default="",
-                    help="comma-separated leaf capacities for --autotune")
+                    help="fix the leaf capacity (0: tuned)")
+    ap.add_argument("--sweep", choices=("lane", "wave"), default=None,
+                    help="fix the sweep flavour (default: tuned)")
     ap.add_argument("--group-k", action="store_true",
-                    help="variable k: answer each k class with its own list size "
-                         "(MKNN_FLAG_GROUP_K)")
+                    help="fix k grouping on (variable k: each k class with its own list size)")
+    ap.add_argument("--autotune", dest="autotune", action="store_true", default=True,
+                    help="choose the schedule during warm-up over %s (default)" % (SCHEDULE_SPACE,))
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="use the stored choice for the workload %s" % (TUNED_SCHEDULE,))
+    ap.add_argument("--th-candidates", default="",
+                    help="comma-separated leaf capacities for the autotuner")
     ap.add_argument("--graph", action="store_true", default=True,
                     help="also replay the ticks as captured HIP graphs (default on)")
     ap.add_argument("--no-graph", dest="graph", action="store_false")
@@ -498,14 +509,32 @@ def main():
             c.query(issuers=iss, ks=ks)
 
     stream = torch.cuda.Stream()
-    cands = (tuple(int(v) for v in args.th_candidates.split(",")) if args.th_candidates
-             else TH_CANDIDATES)
-    th0 = (min(cands) if args.autotune else
-           args.leaf_capacity or TUNED_LEAF_CAPACITY.get(w.name, 0))
-    max_level = args.max_level or TUNED_MAX_LEVEL.get(w.name, 16)
-    ctx = binding.Context(n, nq_max, k, leaf_capacity=th0, k_hint=k, max_level=max_level,
-                          stream=stream.cuda_stream, timing=True, counters=args.counters,
-                          group_k=args.group_k)
+    variable_k = queries[0][1] is not None
+    sched = dict(TUNED_SCHEDULE.get(w.name, {"leaf_capacity": 0, "max_level": 16,
+                                               "sweep": "lane", "group_k": False}))
+    if k > 128:
+        sched["sweep"] = "wave"
+    space = {dim: list(v) for dim, v in SCHEDULE_SPACE.items()}
+    if args.th_candidates:
+        space["leaf_capacity"] = [int(v) for v in args.th_candidates.split(",")]
+    if k > 128:
+        space["sweep"] = []
+    if not variable_k:
+        space["group_k"] = []
+    for dim, val in (("leaf_capacity", args.leaf_capacity or None),
+                     ("max_level", args.max_level or None), ("sweep", args.sweep),
+                     ("group_k", True if args.group_k else None)):
+        if val is not None:
+            sched[dim] = val
+            space[dim] = []
+    # Node tables sized for the smallest leaf capacity and the deepest level
+    # the autotuner may try.
+    th0 = min(space["leaf_capacity"] + [sched["leaf_capacity"] or 10 ** 9])
+    l0 = max(space["max_level"] + [sched["max_level"]])
+    ctx = binding.Context(n, nq_max, k, leaf_capacity=th0 if th0 < 10 ** 9 else 0, k_hint=k,
+                          max_level=l0, stream=stream.cuda_stream, timing=True,
+                          counters=args.counters)
+    ctx.set_schedule(**{d: v for d, v in sched.items() if not (d == "leaf_capacity" and not v)})
 
     def step(s):
         x, y = dev[s % n_ticks]
@@ -515,11 +544,13 @@ def main():
 
     with torch.cuda.stream(stream):
         tune = None
-        if args.autotune:
-            best, times = binding.autotune_leaf_capacity(ctx, step, cands)
-            tune = {"chosen": best, "device_ms_per_tick": {str(t): v for t, v in times.items()}}
-            print("bench: autotuned leaf capacity %d (%s)" % (best, tune), file=sys.stderr,
-                  flush=True)
+        if args.autotune and any(space.values()):
+            best, times = binding.autotune_schedule(
+                ctx, step, space["leaf_capacity"], max_levels=space["max_level"],
+                sweeps=space["sweep"], group_k=space["group_k"], repeats=3, rounds=2)
+            tune = {"chosen": best, "device_ms_per_tick": times}
+            print("bench: autotuned schedule %s" % (best,), file=sys.stderr, flush=True)
+        sched = ctx.schedule()
         for s in range(args.warmup):
             step(s)
         ctx.sync()
@@ -550,7 +581,8 @@ def main():
         "config": {"workload": w.name, "objects": n, "queries_per_tick": nq_mean,
                    "k": k if not subset else "per query, mean %.1f" % (entries_mean / nq_mean),
                    "ticks": w.ticks, "ticks_generated": n_ticks,
-                   "leaf_capacity": st["leaf_capacity"], "max_level": max_level,
+                   "leaf_capacity": st["leaf_capacity"], "max_level": sched["max_level"],
+                   "sweep": sched["sweep"], "group_k": sched["group_k"],
                    "description": w.description},
         "p50_tick_ms": float(np.percentile(lat, 50)),
         "p99_tick_ms": float(np.percentile(lat, 99)),
@@ -561,8 +593,8 @@ def main():
         "leaves": st["leaves"],
         "deepest_level": st["deepest_level"],
         "autotune": tune,
-        "roofline": roofline_entry(w.name, st["leaf_capacity"], max_level, k, kern_ms,
-                                   kern_bytes),
+        "roofline": roofline_entry(w.name, st["leaf_capacity"], sched["max_level"], k, kern_ms,
+                                   kern_bytes, sched["sweep"]),
         "graph": None,
         "cpu_baseline": None,
     }
@@ -574,12 +606,19 @@ def main():
                                 "leaf_sweeps": st["wave_leaf_sweeps"] / wf}
     ctx.close()
 
+    def scheduled_context(strm, timing=False):
+        """A context for another leg of the benchmark, with the schedule
+        the timed ticks ran with."""
+        c = binding.Context(n, nq_max, k, leaf_capacity=sched["leaf_capacity"],
+                            max_level=sched["max_level"], k_hint=k, stream=strm.cuda_stream,
+                            timing=timing)
+        c.set_schedule(**sched)
+        return c
+
     if args.graph:
         # The same ticks, each captured once as a HIP graph (one graph per
         # tick's input buffers) and replayed; no timing events inside.
-        gctx = binding.Context(n, nq_max, k, leaf_capacity=out["config"]["leaf_capacity"],
-                               max_level=max_level, k_hint=k, stream=stream.cuda_stream,
-                               group_k=args.group_k)
+        gctx = scheduled_context(stream)
 
         def gstep(s):
             x, y = dev[s % n_ticks]
@@ -612,10 +651,7 @@ def main():
         # tick's query.  Every tick still builds its index and answers all
         # queries.
         pstreams = [torch.cuda.Stream(), torch.cuda.Stream()]  # default priority
-        pctx = [binding.Context(n, nq_max, k, leaf_capacity=out["config"]["leaf_capacity"],
-                                max_level=max_level, k_hint=k, stream=ps.cuda_stream,
-                                group_k=args.group_k)
-                for ps in pstreams]
+        pctx = [scheduled_context(ps) for ps in pstreams]
 
         def pstep(s):
             c = pctx[s % 2]
@@ -643,9 +679,7 @@ def main():
         # build, else rebuild.  The policy reads the device time of the
         # query two ticks back (waiting for it alone keeps the host two
         # ticks ahead and the GPU busy).
-        rctx = binding.Context(n, nq_max, k, leaf_capacity=out["config"]["leaf_capacity"],
-                               max_level=max_level, k_hint=k, stream=stream.cuda_stream,
-                               timing=True, group_k=args.group_k)
+        rctx = scheduled_context(stream, timing=True)
         pol = binding.ReusePolicy(factor=args.reuse_factor)
 
         def rstep(s):
