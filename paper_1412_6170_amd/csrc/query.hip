@@ -180,18 +180,19 @@ __device__ __forceinline__ void bitonic_merge(uint64_t (&a)[N])
 // a[] and the queue are taken with one min against the reversed queue
 // (which leaves a bitonic sequence) and a bitonic merge sorts them.
 //
-// The threshold is min(a[K-1], cap): cap is one above a key known not to be
-// exceeded by the k-th key (the k-th smallest key of any k other objects
-// bounds it from above), so filtering with it drops nothing that belongs to
-// the answer.  Between merges the threshold may be stale, which only lets
-// more keys into the queue.  The excluded object (the issuer of the query)
-// is queued like any other candidate and removed by id at merge time.
+// The threshold is min(a[K-1], cap), cap being zero for lanes without a
+// query (they never queue anything) and the largest key otherwise.  Between
+// merges the threshold may be stale, which only lets more keys into the
+// queue.  The excluded object (the issuer of the query) must never enter
+// the list: an issuer lies in its own leaf, so it is met only in the first
+// sweep, whose candidates are checked by id as they are offered; a free
+// centre may exclude any object, so then every merge masks it by id.
 template <int K, int P>
 struct Selector {
     uint64_t a[K];
     lds_u64 *q;        // this lane's queue: q[s * kWave], s < P
     uint32_t cnt;
-    uint64_t cap;      // upper bound (exclusive) from the seed
+    uint64_t cap;      // exclusive upper bound of the keys the lane takes
     uint64_t thr;      // min(a[K-1], cap) at the last merge
     uint32_t excl;     // id of the excluded object (the issuer), or kNoExclude
 
@@ -220,6 +221,7 @@ struct Selector {
         cnt += key_less(key, thr) ? 1u : 0u;
     }
 
+    template <bool MASK_EXCL>
     __device__ __forceinline__ void merge()
     {
         // Read every slot (volatile keeps the loads unconditional: slots
@@ -230,7 +232,7 @@ struct Selector {
         for (int s = 0; s < P; ++s) b[s] = vq[s * kWave];
 #pragma unroll
         for (int s = 0; s < P; ++s)
-            b[s] = ((uint32_t)s < cnt && (uint32_t)b[s] != excl) ? b[s] : kKeyMax;
+            b[s] = ((uint32_t)s < cnt && (!MASK_EXCL || (uint32_t)b[s] != excl)) ? b[s] : kKeyMax;
         oddeven_sort<P>(b);
 #pragma unroll
         for (int i = K - P; i < K; ++i) a[i] = key_min(a[i], b[K - 1 - i]);
@@ -255,7 +257,9 @@ struct Selector {
     }
 };
 
-template <int K, int P>
+// FREE: the query has a free centre, whose excluded object may lie in any
+// leaf.
+template <int K, int P, bool FREE>
 struct Lane {
     float qx, qy;
     float pad;   // growth of every node box (drift since the last full build)
@@ -263,16 +267,22 @@ struct Lane {
     Selector<K, P> sel;
     uint32_t n_cand = 0, n_merge = 0, n_node = 0, n_leaf = 0;  // wave-uniform
 
+    // CHECK: the candidate may be the excluded object; its key then gets
+    // the exponent of an infinity (with a nonzero low word it is a NaN,
+    // which compares below no threshold), so it is written but not counted.
+    template <bool CHECK>
     __device__ __forceinline__ void offer(const Point &p)
     {
         const float d2 = sq_dist(qx, qy, p.x, p.y);
-        sel.offer(((uint64_t)__float_as_uint(d2) << 32) | p.id);
+        uint32_t hi = __float_as_uint(d2);
+        if constexpr (CHECK) hi = p.id == sel.excl ? 0x7ff00000u : hi;
+        sel.offer(((uint64_t)hi << 32) | p.id);
     }
 
     __device__ __forceinline__ void merge_if(bool full)
     {
         if (wave_any(full)) {
-            sel.merge();
+            sel.template merge<FREE>();
             ++n_merge;
         }
     }
@@ -285,9 +295,12 @@ struct Lane {
     // Invariant between steps (and between sweeps): every queue holds at
     // most P-2 keys, so a step's two writes stay inside the queue; a merge
     // runs as soon as a queue holds more.
+    // OWN: the first sweep (the leaves holding the queries' centres).
+    template <bool OWN>
     __device__ __forceinline__ void sweep(const Point *__restrict__ pts, int32_t b, int32_t e,
                                           Point *stage)
     {
+        constexpr bool CHECK = OWN && !FREE;
         if (b >= e) return;
         n_cand += (uint32_t)(e - b);
         ++n_leaf;
@@ -303,13 +316,13 @@ struct Lane {
             int32_t j = 0;
             for (; j + 2 <= m; j += 2) {
                 const Point p0 = stage[j], p1 = stage[j + 1];
-                offer(p0);
-                offer(p1);
+                offer<CHECK>(p0);
+                offer<CHECK>(p1);
                 merge_if(sel.cnt > (uint32_t)(P - 2));
             }
             if (j < m) {
                 const Point p0 = stage[j];
-                offer(p0);
+                offer<CHECK>(p0);
                 merge_if(sel.cnt > (uint32_t)(P - 2));
             }
         }
@@ -335,8 +348,8 @@ struct Lane {
 // Positions only move forward (a skip link never points back) and sweep
 // ranges are clamped to the object array, so the walk always terminates
 // inside its buffers.
-template <int K, int P>
-__device__ __forceinline__ int32_t walk_step(Lane<K, P> &ln, const Node *__restrict__ tab,
+template <int K, int P, bool FREE>
+__device__ __forceinline__ int32_t walk_step(Lane<K, P, FREE> &ln, const Node *__restrict__ tab,
                                              int32_t pos, int32_t total,
                                              const Point *__restrict__ pts, int32_t n,
                                              Point *stage)
@@ -351,7 +364,7 @@ __device__ __forceinline__ int32_t walk_step(Lane<K, P> &ln, const Node *__restr
             continue;
         }
         if (nd.leaf >= 0) {
-            ln.sweep(pts, max(nd.begin, 0), min(nd.end, n), stage);
+            ln.template sweep<false>(pts, max(nd.begin, 0), min(nd.end, n), stage);
             return next;
         }
         ++pos;
@@ -363,7 +376,7 @@ __device__ __forceinline__ int32_t walk_step(Lane<K, P> &ln, const Node *__restr
 // and LDS at once instead of waiting for the slowest wavefront of a larger
 // group (wavefront run times differ several-fold between dense and sparse
 // regions).  Tiles are dealt to the XCDs as xcd_tile describes.
-template <int K, int P>
+template <int K, int P, bool FREE>
 __global__ __launch_bounds__(kWave) void k_knn_tiles(QueryArgs qa)
 {
     __shared__ uint64_t s_queue[P * kWave];
@@ -381,7 +394,7 @@ __global__ __launch_bounds__(kWave) void k_knn_tiles(QueryArgs qa)
     if (tile >= tiles) return;  // whole wavefront idle
     const uint32_t t = tile * kWave + lane;
 
-    Lane<K, P> ln;
+    Lane<K, P, FREE> ln;
     ln.active = t < q_count;
     // After refit ticks the objects have moved by up to D per axis since the
     // quadrant boxes were made; grow the boxes by D plus a margin that covers
@@ -420,38 +433,11 @@ __global__ __launch_bounds__(kWave) void k_knn_tiles(QueryArgs qa)
     kq = kq < 1 ? 1 : (kq > K ? K : kq);
     ln.sel.init(kq, (lds_u64 *)&s_queue[lane], excl);
 
-    // Seed: a window of kq + 1 sorted positions around qp holds at least kq
-    // objects other than the excluded one, so the largest of their keys
-    // bounds the k-th key from above.  Inactive lanes keep a zero threshold
-    // and never queue anything.
-    {
-        const int32_t n = (int32_t)qa.n;
-        uint64_t seed = 0;
-        if (n - 1 >= kq) {
-            int32_t w0 = qp - kq / 2;
-            w0 = w0 < 0 ? 0 : (w0 > n - 1 - kq ? n - 1 - kq : w0);
-            // Branch-free: lanes past their window re-read its first object
-            // and contribute a zero key.  K is a multiple of 4: four loads
-            // in flight per step; position K follows the loop.
-            auto seed_step = [&](int s) {
-                const bool in = s <= kq;
-                const Point p = qa.pts[w0 + (in ? s : 0)];
-                const float d2 = sq_dist(ln.qx, ln.qy, p.x, p.y);
-                const uint64_t key = ((uint64_t)__float_as_uint(d2) << 32) | p.id;
-                seed = key_max(seed, (in && p.id != excl) ? key : 0ull);
-            };
-#pragma nounroll
-            for (int s = 0; s < K; s += 4) {
-                seed_step(s);
-                seed_step(s + 1);
-                seed_step(s + 2);
-                seed_step(s + 3);
-            }
-            seed_step(K);
-            ln.sel.set_cap(seed + 1);
-        }
-        ln.sel.set_cap(ln.active ? ln.sel.cap : 0ull);
-    }
+    // Lanes without a query keep a zero threshold and never queue anything.
+    // (A bound on the k-th key from a few nearby objects, tried as a start
+    // threshold, left the merge count unchanged: merges are triggered by
+    // whichever lane's queue fills first.)
+    ln.sel.set_cap(ln.active ? kKeyMax : 0ull);
 
     // Own leaves of the wavefront's queries: a contiguous run of leaves.
     const int32_t my_leaf = qa.leaf_of[qp];
@@ -465,7 +451,8 @@ __global__ __launch_bounds__(kWave) void k_knn_tiles(QueryArgs qa)
     l1 = __builtin_amdgcn_readfirstlane(l1);
 
     // First iteration: the own leaves.
-    ln.sweep(qa.pts, max(qa.leaf_begin[l0], 0), min(qa.leaf_end[l1], (int32_t)qa.n), stage);
+    ln.template sweep<true>(qa.pts, max(qa.leaf_begin[l0], 0), min(qa.leaf_end[l1], (int32_t)qa.n),
+                            stage);
 
     // Subsequent iterations: alternate the two sub-visits.
     const int32_t total = min((int32_t)qa.ctr->n_nodes, qa.node_cap);
@@ -479,7 +466,7 @@ __global__ __launch_bounds__(kWave) void k_knn_tiles(QueryArgs qa)
         // so the list is not duplicated across two inlined sweeps.
         const bool fw = (right && rf < total) || rl >= total;
         const int32_t pos =
-            walk_step<K, P>(ln, fw ? qa.fwd : qa.rev, fw ? rf : rl, total, qa.pts, (int32_t)qa.n,
+            walk_step<K, P, FREE>(ln, fw ? qa.fwd : qa.rev, fw ? rf : rl, total, qa.pts, (int32_t)qa.n,
                             stage);
         rf = fw ? pos : rf;
         rl = fw ? rl : pos;
@@ -487,7 +474,7 @@ __global__ __launch_bounds__(kWave) void k_knn_tiles(QueryArgs qa)
     }
 
     if (wave_any(ln.sel.cnt > 0)) {
-        ln.sel.merge();
+        ln.sel.template merge<FREE>();
         ++ln.n_merge;
     }
     if (qa.counters && lane == 0) {
@@ -647,12 +634,22 @@ void launch_knn(const QueryArgs &qa, int kclass, hipStream_t s)
     const uint32_t tiles = (qa.nq + kWave - 1) / kWave;
     const uint32_t groups = (tiles + kXcds - 1) / kXcds * kXcds;
     const dim3 grid(groups), block(kWave);
+    if (qa.qpts) {
+        switch (kclass) {
+        case 8: k_knn_tiles<8, 8, true><<<grid, block, 0, s>>>(qa); break;
+        case 16: k_knn_tiles<16, 16, true><<<grid, block, 0, s>>>(qa); break;
+        case 32: k_knn_tiles<32, 16, true><<<grid, block, 0, s>>>(qa); break;
+        case 64: k_knn_tiles<64, 32, true><<<grid, block, 0, s>>>(qa); break;
+        default: k_knn_tiles<128, 64, true><<<grid, block, 0, s>>>(qa); break;
+        }
+        return;
+    }
     switch (kclass) {
-    case 8: k_knn_tiles<8, 8><<<grid, block, 0, s>>>(qa); break;
-    case 16: k_knn_tiles<16, 16><<<grid, block, 0, s>>>(qa); break;
-    case 32: k_knn_tiles<32, 16><<<grid, block, 0, s>>>(qa); break;
-    case 64: k_knn_tiles<64, 32><<<grid, block, 0, s>>>(qa); break;
-    default: k_knn_tiles<128, 64><<<grid, block, 0, s>>>(qa); break;
+    case 8: k_knn_tiles<8, 8, false><<<grid, block, 0, s>>>(qa); break;
+    case 16: k_knn_tiles<16, 16, false><<<grid, block, 0, s>>>(qa); break;
+    case 32: k_knn_tiles<32, 16, false><<<grid, block, 0, s>>>(qa); break;
+    case 64: k_knn_tiles<64, 32, false><<<grid, block, 0, s>>>(qa); break;
+    default: k_knn_tiles<128, 64, false><<<grid, block, 0, s>>>(qa); break;
     }
 }
 
