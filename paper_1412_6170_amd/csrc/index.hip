@@ -406,26 +406,28 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_ghist(const uint32_t *__
     }
 }
 
-template <int ITEMS>
-__global__ __launch_bounds__(kSortThreads) void k_radix_pass(
+template <int NT, int ITEMS, bool LAST>
+__global__ __launch_bounds__(NT) void k_radix_pass(
     const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ vals_in,
     uint32_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out, uint32_t n, int shift,
     const uint32_t *__restrict__ ghist, uint64_t *__restrict__ status, uint32_t *__restrict__ ticket,
     uint32_t *__restrict__ err, uint32_t epoch, const float2 *__restrict__ xy,
     Point *__restrict__ pts, float2 *__restrict__ anchor)
 {
-    constexpr int NW = kSortThreads / kWave;
-    constexpr int TILE = kSortThreads * ITEMS;
+    constexpr int NW = NT / kWave;
+    constexpr int TILE = NT * ITEMS;
     constexpr int PER_WAVE = kWave * ITEMS;
+    static_assert(NT >= 2 * kRadixBins, "one thread per digit, as many more gathering");
     __shared__ uint32_t s_keys[TILE];
     __shared__ uint32_t s_vals[TILE];
     __shared__ uint32_t s_wc[NW][kRadixBins];  // per-wavefront digit counts, then bases
     __shared__ uint32_t s_start[kRadixBins];   // start of each digit's run in the tile
     __shared__ uint32_t s_base[kRadixBins];    // destination of each digit's run
+    __shared__ float2 s_pos[LAST ? TILE : 1];  // last pass: positions in tile order
 
     const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
-#pragma unroll
-    for (int q = 0; q < NW; ++q) s_wc[q][t] = 0;
+    const bool digit_thread = t < kRadixBins;  // thread t < 256 owns digit t
+    for (int i = t; i < NW * kRadixBins; i += NT) (&s_wc[0][0])[i] = 0;
     const uint32_t tile = take_ticket(ticket);  // also orders the clearing above
     const uint32_t base = tile * (uint32_t)TILE;
     const uint32_t n_valid = min((uint32_t)TILE, n - base);
@@ -459,17 +461,20 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_pass(
 
     // Thread t: digit t.  Per-wavefront counts become per-wavefront bases.
     uint32_t cnt = 0;
+    if (digit_thread) {
 #pragma unroll
-    for (int q = 0; q < NW; ++q) {
-        const uint32_t c = s_wc[q][t];
-        s_wc[q][t] = cnt;
-        cnt += c;
+        for (int q = 0; q < NW; ++q) {
+            const uint32_t c = s_wc[q][t];
+            s_wc[q][t] = cnt;
+            cnt += c;
+        }
     }
     // Publish this tile's count of digit t (padding excluded) before
     // anything else, so later tiles can resolve while this one reorders.
     const uint32_t real = cnt - (t == kRadixBins - 1 ? (uint32_t)TILE - n_valid : 0u);
-    lb_publish(status + t, kRadixBins, tile, real);
-    s_start[t] = block_excl_scan<kSortThreads>(cnt, nullptr);
+    if (digit_thread) lb_publish(status + t, kRadixBins, tile, real);
+    const uint32_t start = block_excl_scan<NT>(cnt, nullptr);
+    if (digit_thread) s_start[t] = start;
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
@@ -480,19 +485,30 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_pass(
     }
 
     // Offset of digit t: keys of smaller digits anywhere, plus keys of digit
-    // t in earlier tiles.
+    // t in earlier tiles.  The digit threads wait for the earlier tiles.
+    // In the last pass the other threads meanwhile fetch the position of
+    // every object of the tile by id (random reads) into LDS: in waves of
+    // their own, so the waits of the look-back, which count that wave's
+    // memory reads in order, do not wait for them too.
     {
         uint32_t count = 0;
+        if (digit_thread) {
 #pragma unroll
-        for (int c = 0; c < kGhistCopies; ++c) count += ghist[c * kGhistStride + t];
-        const uint32_t below = block_excl_scan<kSortThreads>(count, nullptr);
-        const uint64_t before = lb_resolve(status + t, kRadixBins, tile, real, err, epoch);
-        s_base[t] = below + (uint32_t)before;
+            for (int c = 0; c < kGhistCopies; ++c) count += ghist[c * kGhistStride + t];
+        }
+        const uint32_t below = block_excl_scan<NT>(count, nullptr);
+        if (digit_thread) {
+            const uint64_t before = lb_resolve(status + t, kRadixBins, tile, real, err, epoch);
+            s_base[t] = below + (uint32_t)before;
+        } else if constexpr (LAST) {
+            for (uint32_t lp = t - kRadixBins; lp < n_valid; lp += NT - kRadixBins)
+                s_pos[lp] = xy[s_vals[lp]];
+        }
     }
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
-        const uint32_t lp = j * kSortThreads + t;
+        const uint32_t lp = j * NT + t;
         if (lp < n_valid) {
             const uint32_t k = s_keys[lp];
             const uint32_t d = (k >> shift) & (kRadixBins - 1);
@@ -505,8 +521,8 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_pass(
                 continue;
             }
             keys_out[dst] = k;
-            if (pts) {
-                const float2 q = xy[v];
+            if constexpr (LAST) {
+                const float2 q = s_pos[lp];
                 Point r;
                 r.x = q.x;
                 r.y = q.y;
@@ -525,7 +541,7 @@ static int sort_items(int64_t n) { return n >= kSortLargeKeys ? kSortItemsLarge 
 
 int64_t radix_tiles(int64_t n)
 {
-    const int64_t tile = (int64_t)kSortThreads * sort_items(n);
+    const int64_t tile = (int64_t)kPassThreads * sort_items(n);
     return n > 0 ? (n + tile - 1) / tile : 1;
 }
 
@@ -534,7 +550,7 @@ int64_t radix_tiles(int64_t n)
 // tiles start).
 static int64_t radix_tiles_bound(int64_t n)
 {
-    const int64_t tile = (int64_t)kSortThreads * kSortItems;
+    const int64_t tile = (int64_t)kPassThreads * kSortItems;
     return n > 0 ? (n + tile - 1) / tile : 1;
 }
 
@@ -551,8 +567,12 @@ int launch_radix_sort(const SortBuffers &b, int64_t n, int bits, hipStream_t s, 
     const bool large = sort_items(n) == kSortItemsLarge;
     for (int p = 0; p < passes; ++p) {
         const bool last = p == passes - 1;
-        auto pass = large ? k_radix_pass<kSortItemsLarge> : k_radix_pass<kSortItems>;
-        pass<<<ntiles, kSortThreads, 0, s>>>(
+        const bool rec = last && pts;  // this pass writes the object records
+        auto pass = large ? (rec ? k_radix_pass<kPassThreads, kSortItemsLarge, true>
+                                 : k_radix_pass<kPassThreads, kSortItemsLarge, false>)
+                          : (rec ? k_radix_pass<kPassThreads, kSortItems, true>
+                                 : k_radix_pass<kPassThreads, kSortItems, false>);
+        pass<<<ntiles, kPassThreads, 0, s>>>(
             b.keys[cur], b.vals[cur], b.keys[cur ^ 1], b.vals[cur ^ 1], (uint32_t)n,
             low_bit + kRadixBits * p, b.ghist + p * kRadixBins,
             b.status + (uint64_t)p * ntiles * kRadixBins, b.tickets + p, b.err, b.epoch,

@@ -12,12 +12,14 @@ constexpr int kCodeLevels = 16;       // Morton codes on the 2^16 x 2^16 grid
 constexpr int kWave = 64;             // CDNA wavefront width
 constexpr int kRadixBits = 8;         // LSD radix sort digit
 constexpr int kRadixBins = 1 << kRadixBits;
-constexpr int kSortThreads = 256;     // one workgroup = 4 waves
+constexpr int kSortThreads = 256;     // digit-count workgroup = 4 waves
+// A radix pass tile: 8 waves, so each wave ranks its keys in 8 rounds.
+constexpr int kPassThreads = 512;
 // Keys per thread of a radix tile: 4096-key tiles, or 8192-key tiles from
 // kSortLargeKeys keys on (fewer tiles shorten the look-back chains of large
 // sorts; below it the larger tiles leave CUs idle).
-constexpr int kSortItems = 16;
-constexpr int kSortItemsLarge = 32;
+constexpr int kSortItems = 8;
+constexpr int kSortItemsLarge = 16;
 constexpr int64_t kSortLargeKeys = int64_t(1) << 21;
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;
