@@ -21,8 +21,8 @@ constexpr int kPassThreads = 512;
 constexpr int kSortItems = 8;
 constexpr int kSortItemsLarge = 16;
 constexpr int64_t kSortLargeKeys = int64_t(1) << 21;
-constexpr int kScanThreads = 256;
-constexpr int kScanItems = 8;
+constexpr int kScanThreads = 1024;
+constexpr int kScanItems = 2;
 constexpr int kScanTile = kScanThreads * kScanItems;
 
 // One object in sorted (Morton) order.  Array of 16-byte records so one
