@@ -46,20 +46,27 @@ def test_query_kernel_bytes():
     assert bench.query_kernel_bytes(1_000_000, 1_000_000, 32_000_000) == 12_000_000 + 260_000_000
 
 
-@pytest.mark.parametrize("workload", ["clustered_1m", "uniform_10k"])
-def test_traffic_only_for_matching_sources(workload):
-    m = bench.MEASURED_TRAFFIC
-    got = bench.measured_traffic(workload, m["leaf_capacity"], m.get("max_level", 16))
-    if workload != m["workload"] or m["digest"] != bench.query_source_digest():
-        assert got is None
-    else:
-        assert got == m["fetch_bytes"] + m["write_bytes"]
+def _entries(digest):
+    return [dict(digest=digest, workload="clustered_1m", leaf_capacity=48, max_level=14,
+                 fetch_bytes=10, write_bytes=20, valu_insts=1_000_000),
+            dict(digest="stale-digest", workload="clustered_1m", leaf_capacity=64, max_level=12,
+                 fetch_bytes=1, write_bytes=2, valu_insts=5)]
 
 
-def test_traffic_needs_the_same_maximum_level():
-    m = bench.MEASURED_TRAFFIC
-    other = 16 if m.get("max_level", 16) != 16 else 12
-    assert bench.measured_traffic(m["workload"], m["leaf_capacity"], other) is None
+def test_traffic_only_for_matching_sources_and_schedule(monkeypatch):
+    monkeypatch.setattr(bench, "MEASURED_TRAFFIC", _entries(bench.query_source_digest()))
+    assert bench.measured_traffic("clustered_1m", 48, 14) == 30
+    assert bench.measured_traffic("clustered_1m", 48, 12) is None        # other level
+    assert bench.measured_traffic("clustered_1m", 64, 12) is None        # code changed since
+    assert bench.measured_traffic("uniform_10k", 48, 14) is None         # other workload
+    assert bench.measured_traffic("clustered_1m", 48, 14, "wave") is None  # other flavour
+
+
+def test_stored_traffic_entries_are_well_formed():
+    for m in bench.MEASURED_TRAFFIC:
+        assert len(m["digest"]) == 16
+        assert m["fetch_bytes"] > 0 and m["write_bytes"] > 0 and m["valu_insts"] > 0
+        assert m["leaf_capacity"] >= 1 and 1 <= m["max_level"] <= 16
 
 
 def test_digest_ignores_comments_not_code():
@@ -75,32 +82,30 @@ def test_digest_ignores_comments_not_code():
     assert bench.query_source_digest(changed.get) != base
 
 
-def test_valu_issue_fraction():
-    m = bench.MEASURED_TRAFFIC
+def test_valu_issue_fraction(monkeypatch):
+    monkeypatch.setattr(bench, "MEASURED_TRAFFIC", _entries(bench.query_source_digest()))
     ms = 0.5
-    got = bench.valu_issue(m["workload"], m["leaf_capacity"], m.get("max_level", 16), ms)
-    if m["digest"] != bench.query_source_digest():
-        assert got is None
-        return
+    got = bench.valu_issue("clustered_1m", 48, 14, ms)
     assert got["bound"] == "alu"
-    assert abs(got["frac"] - m["valu_insts"] * 64 / (ms * 1e-3) / (256 * 4 * 16 * 2.4e9)) < 1e-12
-    assert bench.valu_issue("uniform_10k", m["leaf_capacity"], 16, ms) is None
+    assert abs(got["frac"] - 1_000_000 * 64 / (ms * 1e-3) / (256 * 4 * 16 * 2.4e9)) < 1e-12
+    assert bench.valu_issue("clustered_1m", 64, 12, ms) is None
+    assert bench.valu_issue("uniform_10k", 48, 14, ms) is None
 
 
-def test_roofline_names_the_closer_roof():
-    m = bench.MEASURED_TRAFFIC
-    L = m.get("max_level", 16)
-    r = bench.roofline_entry(m["workload"], m["leaf_capacity"], L, 32, 0.44, 272_000_000)
-    assert abs(r["hbm_frac" if r["bound"] == "alu" else "frac"]
-               - 272_000_000 / 0.44e-3 / 8e12) < 1e-9
-    v = bench.valu_issue(m["workload"], m["leaf_capacity"], L, 0.44)
-    if v is None:
-        assert r["bound"] == "hbm"
-    else:
-        assert r["bound"] == ("alu" if v["frac"] > r.get("hbm_frac", r["frac"]) else "hbm")
+def test_roofline_names_the_closer_roof(monkeypatch):
+    monkeypatch.setattr(bench, "MEASURED_TRAFFIC", _entries(bench.query_source_digest()))
+    # A large instruction count: the VALU roof is the closer one.
+    monkeypatch.setitem(bench.MEASURED_TRAFFIC[0], "valu_insts", 190_000_000)
+    r = bench.roofline_entry("clustered_1m", 48, 14, 32, 0.44, 272_000_000)
+    assert r["bound"] == "alu" and r["traffic"] == 30
+    assert abs(r["hbm_frac"] - 272_000_000 / 0.44e-3 / 8e12) < 1e-9
+    # A small one: the HBM roof is.
+    monkeypatch.setitem(bench.MEASURED_TRAFFIC[0], "valu_insts", 10)
+    r = bench.roofline_entry("clustered_1m", 48, 14, 32, 0.44, 272_000_000)
+    assert r["bound"] == "hbm" and abs(r["frac"] - 272_000_000 / 0.44e-3 / 8e12) < 1e-9
     # A configuration without a stored instruction count falls back to HBM.
     r2 = bench.roofline_entry("uniform_10k", 32, 16, 8, 0.06, 1_000_000)
-    assert r2["bound"] == "hbm" and r2["unit"] == "GB/s"
+    assert r2["bound"] == "hbm" and r2["unit"] == "GB/s" and r2["traffic"] is None
 
 
 def test_cpu_model_reads_the_host():
