@@ -48,13 +48,13 @@ TH_CANDIDATES = (16, 24, 32, 48, 64, 96, 128, 192)
 # one query per wavefront: Sec. 4.2.1's cached and coalesced-writes
 # variants) and, for variable k, k grouping.
 SCHEDULE_SPACE = {"leaf_capacity": TH_CANDIDATES, "max_level": (12, 14, 16),
-                  "sweep": ("lane", "wave"), "group_k": (False, True)}
+                  "sweep": ("lane", "wave", "group"), "group_k": (False, True)}
 # The autotuner's choice on MI355X per workload, used with --no-autotune.
 TUNED_SCHEDULE = {
     "uniform_10k": {"leaf_capacity": 32, "max_level": 16, "sweep": "lane", "group_k": False},
     "clustered_1m": {"leaf_capacity": 48, "max_level": 14, "sweep": "lane", "group_k": False},
     "network_4m": {"leaf_capacity": 64, "max_level": 12, "sweep": "lane", "group_k": False},
-    "mixed_16m": {"leaf_capacity": 64, "max_level": 16, "sweep": "lane", "group_k": False},
+    "mixed_16m": {"leaf_capacity": 64, "max_level": 16, "sweep": "group", "group_k": False},
 }
 CPU_SAMPLE_SECONDS = 10.0
 
@@ -84,7 +84,7 @@ def code_only(text):
     return " ".join(text.split())
 
 
-DIGEST_FILES = ("query.hip", "query_wave.hip", "query.hpp", "query_device.hpp",
+DIGEST_FILES = ("query.hip", "query_wave.hip", "query_group.hip", "query.hpp", "query_device.hpp",
                 "mknn_internal.hpp")
 
 
@@ -427,7 +427,7 @@ def main():
                     help="fix the maximum quadtree level 1..16 (0: tuned)")
     ap.add_argument("--leaf-capacity", type=int, default=0,
                     help="fix the leaf capacity (0: tuned)")
-    ap.add_argument("--sweep", choices=("lane", "wave"), default=None,
+    ap.add_argument("--sweep", choices=("lane", "wave", "group"), default=None,
                     help="fix the sweep flavour (default: tuned)")
     ap.add_argument("--group-k", action="store_true",
                     help="fix k grouping on (variable k: each k class with its own list size)")
@@ -520,13 +520,13 @@ def main():
     variable_k = queries[0][1] is not None
     sched = dict(TUNED_SCHEDULE.get(w.name, {"leaf_capacity": 0, "max_level": 16,
                                                "sweep": "lane", "group_k": False}))
-    if k > 128:
-        sched["sweep"] = "wave"
+    if k > 128 and sched["sweep"] == "lane":
+        sched["sweep"] = "group"
     space = {dim: list(v) for dim, v in SCHEDULE_SPACE.items()}
     if args.th_candidates:
         space["leaf_capacity"] = [int(v) for v in args.th_candidates.split(",")]
     if k > 128:
-        space["sweep"] = []
+        space["sweep"] = ["wave", "group"]
     if not variable_k:
         space["group_k"] = []
     for dim, val in (("leaf_capacity", args.leaf_capacity or None),

@@ -81,11 +81,18 @@ extern "C" {
  * registers (k <= 128).  WAVE is the "coalesced writes" flavour: one query
  * per wavefront, candidates checked by the lanes side by side, list updates
  * orchestrated with ballots through an LDS buffer, rows written by
- * consecutive lanes (any k up to MKNN_K_LIMIT).  AUTO takes LANE up to
- * k = 128 and WAVE above.  Results are the same in every flavour. */
+ * consecutive lanes (any k up to MKNN_K_LIMIT).  GROUP is the coalesced-
+ * writes flavour with a query per group of k/16 lanes (rounded up to a
+ * power of two, at least 2): its list spread 16 keys per lane over the
+ * group, 64 / group queries per wavefront sharing their candidates, lists
+ * merged by bitonic networks across the group's lanes (any k up to
+ * MKNN_K_LIMIT).  AUTO takes LANE up to k = 64 and GROUP above; LANE
+ * itself hands k above 128 to WAVE.  Results are the same in every
+ * flavour. */
 #define MKNN_SWEEP_AUTO 0
 #define MKNN_SWEEP_LANE 1
 #define MKNN_SWEEP_WAVE 2
+#define MKNN_SWEEP_GROUP 3
 
 /* mknn_config.flags */
 /* Record per-phase device times (mknn_stats): HIP events on the context's
@@ -336,8 +343,8 @@ MKNN_API int mknn_set_leaf_capacity(mknn_ctx *ctx, int32_t th);
  * Tuning knobs of a context, for an autotuner (results never depend on
  * them).  leaf_capacity is th (Sec. 4.1); max_level is l_max (Sec. 4.1,
  * 1..16); sweep is an MKNN_SWEEP_* flavour (LANE applies to k <= 128;
- * larger k always use WAVE); group_k != 0 behaves as MKNN_FLAG_GROUP_K
- * (variable-k queries answered per k class, lane flavour only).  The
+ * larger k then use WAVE); group_k != 0 behaves as MKNN_FLAG_GROUP_K
+ * (variable-k queries answered per k class, lane or group flavour).  The
  * index settings take effect at the next mknn_advance_tick, the sweep
  * settings at the next query.
  */

@@ -24,7 +24,9 @@ MKNN_K_LIMIT = 1024
 MKNN_SWEEP_AUTO = 0
 MKNN_SWEEP_LANE = 1
 MKNN_SWEEP_WAVE = 2
-SWEEPS = {"auto": MKNN_SWEEP_AUTO, "lane": MKNN_SWEEP_LANE, "wave": MKNN_SWEEP_WAVE}
+MKNN_SWEEP_GROUP = 3
+SWEEPS = {"auto": MKNN_SWEEP_AUTO, "lane": MKNN_SWEEP_LANE, "wave": MKNN_SWEEP_WAVE,
+          "group": MKNN_SWEEP_GROUP}
 STATUS = {0: "MKNN_OK", -1: "MKNN_E_INVAL", -2: "MKNN_E_RANGE", -3: "MKNN_E_STATE",
           -4: "MKNN_E_CAPACITY", -5: "MKNN_E_NOMEM", -6: "MKNN_E_DEVICE"}
 

@@ -14,7 +14,8 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = [os.path.join(HERE, "csrc", f) for f in ("index.hip", "query.hip", "query_wave.hip", "capi.hip")]
+SRC = [os.path.join(HERE, "csrc", f) for f in ("index.hip", "query.hip", "query_wave.hip",
+                                              "query_group.hip", "capi.hip")]
 OUT = os.path.join(HERE, "libmknn.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -324,17 +324,35 @@ int mark_main(mknn_ctx *c, bool prepared)
     return prepared ? mark(c, 3) : MKNN_OK;
 }
 
-// The one-query-per-wavefront flavour answers every k above the lane
-// kernel's 128 keys, and any k when the schedule asks for it.
+// The flavour a query runs with: the schedule's, except that the lane
+// flavour hands lists above its 128 keys to the one-query-per-wavefront
+// flavour.  AUTO takes one query per lane up to k = 64 and a group of lanes
+// per query above, where a lane-private list would leave at most two
+// wavefronts per SIMD (k = 128 on mixed_16m: 36 ms per query kernel
+// against 45 ms).
+int sweep_flavour(const mknn_ctx *c, int kmax_call)
+{
+    if (c->sweep == MKNN_SWEEP_GROUP || c->sweep == MKNN_SWEEP_WAVE) return c->sweep;
+    if (c->sweep == MKNN_SWEEP_AUTO) return kmax_call > 64 ? MKNN_SWEEP_GROUP : MKNN_SWEEP_LANE;
+    return kmax_call > 128 ? MKNN_SWEEP_WAVE : MKNN_SWEEP_LANE;
+}
+
 bool use_wave_sweep(const mknn_ctx *c, int kmax_call)
 {
-    return kmax_call > 128 || c->sweep == MKNN_SWEEP_WAVE;
+    return sweep_flavour(c, kmax_call) == MKNN_SWEEP_WAVE;
+}
+
+// One k class of queries (or all of them) with list size kclass_k.
+void launch_class(const mknn_ctx *c, const QueryArgs &qa, int kclass_k, int flavour)
+{
+    if (flavour == MKNN_SWEEP_WAVE) launch_knn_wave(qa, k_class_wave(kclass_k), c->stream);
+    else if (flavour == MKNN_SWEEP_GROUP) launch_knn_group(qa, k_class_group(kclass_k), c->stream);
+    else launch_knn(qa, k_class(kclass_k), c->stream);
 }
 
 void launch_sweep(const mknn_ctx *c, const QueryArgs &qa, int kmax_call)
 {
-    if (use_wave_sweep(c, kmax_call)) launch_knn_wave(qa, k_class_wave(kmax_call), c->stream);
-    else launch_knn(qa, k_class(kmax_call), c->stream);
+    launch_class(c, qa, kmax_call, sweep_flavour(c, kmax_call));
 }
 
 }  // namespace
@@ -835,7 +853,7 @@ int mknn_query(mknn_ctx *c, const int32_t *issuers, const int32_t *ks, int64_t n
         for (int cls = 0; cls <= top; ++cls) {
             if (!(present & (1u << cls))) continue;
             qa.klass = cls;
-            launch_knn(qa, 8 << cls, c->stream);
+            launch_class(c, qa, 8 << cls, sweep_flavour(c, kmax_call));
         }
     } else {
         launch_sweep(c, qa, kmax_call);
@@ -998,7 +1016,7 @@ int mknn_set_schedule(mknn_ctx *c, const mknn_schedule *sc)
     if (sc->max_level < 1 || sc->max_level > kCodeLevels)
         return fail(c, MKNN_E_INVAL, "max_level must be in 1..16%s");
     if (sc->sweep != MKNN_SWEEP_AUTO && sc->sweep != MKNN_SWEEP_LANE &&
-        sc->sweep != MKNN_SWEEP_WAVE)
+        sc->sweep != MKNN_SWEEP_WAVE && sc->sweep != MKNN_SWEEP_GROUP)
         return fail(c, MKNN_E_INVAL, "unknown sweep flavour%s");
     if (node_capacity(c->cfg.n_max, sc->leaf_capacity, sc->max_level) > c->ix.node_cap)
         return fail(c, MKNN_E_CAPACITY, "schedule needs larger node tables than allocated%s");

@@ -42,14 +42,6 @@
 
 namespace mknn {
 
-// Compare-exchange on keys: afterwards lo <= hi.
-__device__ __forceinline__ void cmp_swap(uint64_t &lo, uint64_t &hi)
-{
-    const uint64_t t = key_min(lo, hi);
-    hi = key_max(lo, hi);
-    lo = t;
-}
-
 // Sorting networks on register arrays.  They are expanded with templates
 // (fold expressions over the element indices) rather than unrolled loops, so
 // every index is a compile-time constant whatever the size: an array
@@ -88,59 +80,6 @@ __device__ __forceinline__ void bitonic_sort(uint64_t (&b)[N])
         sort_strides<N, SIZE, SIZE / 2>(b);
         bitonic_sort<N, SIZE * 2>(b);
     }
-}
-
-// Batcher's odd-even merge sort (N a power of two): fewer compare-exchanges
-// than the bitonic network (63 instead of 80 for N = 16), all ascending.
-// The comparator list is generated at compile time.
-template <int N>
-struct OddEvenNet {
-    int lo[N * N], hi[N * N];  // generous bound on the comparator count
-    int count = 0;
-    constexpr void add(int a, int b)
-    {
-        lo[count] = a;
-        hi[count] = b;
-        ++count;
-    }
-    constexpr void merge(int base, int n, int r)
-    {
-        const int m = r * 2;
-        if (m < n) {
-            merge(base, n, m);
-            merge(base + r, n, m);
-            for (int i = base + r; i + r < base + n; i += m) add(i, i + r);
-        } else {
-            add(base, base + r);
-        }
-    }
-    constexpr void sort(int base, int n)
-    {
-        if (n > 1) {
-            const int m = n / 2;
-            sort(base, m);
-            sort(base + m, m);
-            merge(base, n, 1);
-        }
-    }
-    constexpr OddEvenNet() : lo(), hi() { sort(0, N); }
-};
-
-template <int N>
-struct OddEven {
-    static constexpr OddEvenNet<N> net{};
-};
-
-template <int N, int... I>
-__device__ __forceinline__ void oddeven_apply(uint64_t (&b)[N], std::integer_sequence<int, I...>)
-{
-    (cmp_swap(b[OddEven<N>::net.lo[I]], b[OddEven<N>::net.hi[I]]), ...);
-}
-
-template <int N>
-__device__ __forceinline__ void oddeven_sort(uint64_t (&b)[N])
-{
-    oddeven_apply<N>(b, std::make_integer_sequence<int, OddEven<N>::net.count>{});
 }
 
 template <int N, int OFF, int STRIDE, int I>

@@ -84,6 +84,10 @@ int k_class(int k);
 // kernel for a largest k.
 int k_class_wave(int k);
 void launch_knn_wave(const QueryArgs &qa, int kclass, hipStream_t s);
+// List size (32, 64, ..., 1024 keys: 16 per lane of a group of 2 to 64
+// lanes) of the group-per-query kernel for a largest k.
+int k_class_group(int k);
+void launch_knn_group(const QueryArgs &qa, int kclass, hipStream_t s);
 void launch_point_prep(const PointPrep &p, hipStream_t s);
 void launch_point_place(const uint32_t *codes, const uint32_t *rows, uint32_t nq, const float *qx,
                         const float *qy, const int32_t *exclude, const Point *pts, uint32_t n,

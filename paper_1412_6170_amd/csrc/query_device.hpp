@@ -4,6 +4,8 @@
 // distance and bound computations separately rounded.
 #pragma once
 
+#include <utility>
+
 #include "mknn_internal.hpp"
 
 #pragma clang fp contract(off)
@@ -73,7 +75,153 @@ __device__ __forceinline__ float box_lower_bound(float qx, float qy, const Node 
     return ax + ay;
 }
 
+// Compare-exchange on keys: afterwards lo <= hi.
+__device__ __forceinline__ void cmp_swap(uint64_t &lo, uint64_t &hi)
+{
+    const uint64_t t = key_min(lo, hi);
+    hi = key_max(lo, hi);
+    lo = t;
+}
+
+// Batcher's odd-even merge sort (N a power of two): fewer compare-exchanges
+// than the bitonic network (63 instead of 80 for N = 16), all ascending.
+// The comparator list is generated at compile time.
+template <int N>
+struct OddEvenNet {
+    int lo[N * N], hi[N * N];  // generous bound on the comparator count
+    int count = 0;
+    constexpr void add(int a, int b)
+    {
+        lo[count] = a;
+        hi[count] = b;
+        ++count;
+    }
+    constexpr void merge(int base, int n, int r)
+    {
+        const int m = r * 2;
+        if (m < n) {
+            merge(base, n, m);
+            merge(base + r, n, m);
+            for (int i = base + r; i + r < base + n; i += m) add(i, i + r);
+        } else {
+            add(base, base + r);
+        }
+    }
+    constexpr void sort(int base, int n)
+    {
+        if (n > 1) {
+            const int m = n / 2;
+            sort(base, m);
+            sort(base + m, m);
+            merge(base, n, 1);
+        }
+    }
+    constexpr OddEvenNet() : lo(), hi() { sort(0, N); }
+};
+
+template <int N>
+struct OddEven {
+    static constexpr OddEvenNet<N> net{};
+};
+
+template <int N, int... I>
+__device__ __forceinline__ void oddeven_apply(uint64_t (&b)[N], std::integer_sequence<int, I...>)
+{
+    (cmp_swap(b[OddEven<N>::net.lo[I]], b[OddEven<N>::net.hi[I]]), ...);
+}
+
+template <int N>
+__device__ __forceinline__ void oddeven_sort(uint64_t (&b)[N])
+{
+    oddeven_apply<N>(b, std::make_integer_sequence<int, OddEven<N>::net.count>{});
+}
+
 __device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
+
+__device__ __forceinline__ uint64_t shfl_xor_key(uint64_t v, int m)
+{
+    const int lo = __shfl_xor((int)(uint32_t)v, m, kWave);
+    const int hi = __shfl_xor((int)(uint32_t)(v >> 32), m, kWave);
+    return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+__device__ __forceinline__ uint64_t shfl_key(uint64_t v, int src)
+{
+    const int lo = __shfl((int)(uint32_t)v, src, kWave);
+    const int hi = __shfl((int)(uint32_t)(v >> 32), src, kWave);
+    return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+__device__ __forceinline__ uint64_t readlane_key(uint64_t v, int lane)
+{
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, lane);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), lane);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Bitonic networks over N keys (a power of two) held PL per lane by N / PL
+// consecutive lanes in the blocked layout: key i sits in lane i / PL of the
+// group, register i % PL; `idx` is the lane's index in its group (groups
+// are aligned, so partners found by xor-ing the lane id stay inside).  A
+// stage pairs i with i ^ STRIDE and orders the pair ascending where
+// (i & SIZE) == 0 (SIZE = 0: every pair ascending, as in the last stage of
+// a sort and in a merge).  Partners at a distance below PL are in the same
+// lane; farther partners are in lane idx ^ (STRIDE / PL), same register, and
+// each side keeps the minimum or the maximum.  Expanded with templates so
+// every register index is static.
+template <int PL, int SIZE, int STRIDE, int R>
+__device__ __forceinline__ void wstage_one(uint64_t (&v)[PL], int idx)
+{
+    bool asc;
+    if constexpr (SIZE == 0) asc = true;
+    else if constexpr (SIZE < PL) asc = (R & SIZE) == 0;
+    else asc = ((idx * PL) & SIZE) == 0;  // R < PL <= SIZE: no carry into bit SIZE
+    if constexpr (STRIDE < PL) {
+        constexpr int R2 = R ^ STRIDE;
+        if constexpr (R2 > R) {
+            const uint64_t lo = key_min(v[R], v[R2]);
+            const uint64_t hi = key_max(v[R], v[R2]);
+            v[R] = asc ? lo : hi;
+            v[R2] = asc ? hi : lo;
+        }
+    } else {
+        constexpr int M = STRIDE / PL;
+        const uint64_t w = shfl_xor_key(v[R], M);
+        const bool lower = (idx & M) == 0;
+        v[R] = (lower == asc) ? key_min(v[R], w) : key_max(v[R], w);
+    }
+}
+
+template <int PL, int SIZE, int STRIDE, int... R>
+__device__ __forceinline__ void wstage(uint64_t (&v)[PL], int idx, std::integer_sequence<int, R...>)
+{
+    (wstage_one<PL, SIZE, STRIDE, R>(v, idx), ...);
+}
+
+template <int PL, int SIZE, int STRIDE>
+__device__ __forceinline__ void wstrides(uint64_t (&v)[PL], int idx)
+{
+    wstage<PL, SIZE, STRIDE>(v, idx, std::make_integer_sequence<int, PL>{});
+    if constexpr (STRIDE > 1) wstrides<PL, SIZE, STRIDE / 2>(v, idx);
+}
+
+// Sort all N keys of the group ascending.
+template <int PL, int N, int SIZE = 2>
+__device__ __forceinline__ void net_sort(uint64_t (&v)[PL], int idx)
+{
+    if constexpr (SIZE <= N) {
+        wstrides<PL, (SIZE == N ? 0 : SIZE), SIZE / 2>(v, idx);
+        net_sort<PL, N, SIZE * 2>(v, idx);
+    }
+}
+
+// Sort a bitonic sequence of N keys ascending (half-cleaner cascade).
+template <int PL, int N>
+__device__ __forceinline__ void net_merge(uint64_t (&v)[PL], int idx)
+{
+    wstrides<PL, 0, N / 2>(v, idx);
+}
+
 
 // Tile order is XCD-aware: workgroups are dealt round-robin to the 8 XCDs
 // (workgroup b runs on XCD b mod 8), so for T tiles workgroup b takes tile

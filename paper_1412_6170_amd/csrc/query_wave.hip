@@ -43,81 +43,6 @@
 
 namespace mknn {
 
-__device__ __forceinline__ uint64_t shfl_xor_key(uint64_t v, int m)
-{
-    const int lo = __shfl_xor((int)(uint32_t)v, m, kWave);
-    const int hi = __shfl_xor((int)(uint32_t)(v >> 32), m, kWave);
-    return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
-}
-
-__device__ __forceinline__ uint64_t readlane_key(uint64_t v, int lane)
-{
-    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, lane);
-    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), lane);
-    return ((uint64_t)hi << 32) | lo;
-}
-
-// Bitonic networks over N = 64 * PL keys in the blocked layout: key i sits
-// in lane i / PL, register i % PL.  A stage pairs i with i ^ STRIDE and
-// orders the pair ascending where (i & SIZE) == 0 (SIZE = 0: every pair
-// ascending, as in the last stage of a sort and in a merge).  Partners at a
-// distance below PL are in the same lane; farther partners are in lane
-// lane ^ (STRIDE / PL), same register, and each side keeps the minimum or
-// the maximum.  Expanded with templates so every register index is static.
-template <int PL, int SIZE, int STRIDE, int R>
-__device__ __forceinline__ void wstage_one(uint64_t (&v)[PL], int lane)
-{
-    bool asc;
-    if constexpr (SIZE == 0) asc = true;
-    else if constexpr (SIZE < PL) asc = (R & SIZE) == 0;
-    else asc = ((lane * PL) & SIZE) == 0;  // R < PL <= SIZE: no carry into bit SIZE
-    if constexpr (STRIDE < PL) {
-        constexpr int R2 = R ^ STRIDE;
-        if constexpr (R2 > R) {
-            const uint64_t lo = key_min(v[R], v[R2]);
-            const uint64_t hi = key_max(v[R], v[R2]);
-            v[R] = asc ? lo : hi;
-            v[R2] = asc ? hi : lo;
-        }
-    } else {
-        constexpr int M = STRIDE / PL;
-        const uint64_t w = shfl_xor_key(v[R], M);
-        const bool lower = (lane & M) == 0;
-        v[R] = (lower == asc) ? key_min(v[R], w) : key_max(v[R], w);
-    }
-}
-
-template <int PL, int SIZE, int STRIDE, int... R>
-__device__ __forceinline__ void wstage(uint64_t (&v)[PL], int lane, std::integer_sequence<int, R...>)
-{
-    (wstage_one<PL, SIZE, STRIDE, R>(v, lane), ...);
-}
-
-template <int PL, int SIZE, int STRIDE>
-__device__ __forceinline__ void wstrides(uint64_t (&v)[PL], int lane)
-{
-    wstage<PL, SIZE, STRIDE>(v, lane, std::make_integer_sequence<int, PL>{});
-    if constexpr (STRIDE > 1) wstrides<PL, SIZE, STRIDE / 2>(v, lane);
-}
-
-// Sort all 64 * PL keys ascending.
-template <int PL, int SIZE = 2>
-__device__ __forceinline__ void wave_sort(uint64_t (&v)[PL], int lane)
-{
-    constexpr int N = kWave * PL;
-    if constexpr (SIZE <= N) {
-        wstrides<PL, (SIZE == N ? 0 : SIZE), SIZE / 2>(v, lane);
-        wave_sort<PL, SIZE * 2>(v, lane);
-    }
-}
-
-// Sort a bitonic sequence of 64 * PL keys ascending (half-cleaner cascade).
-template <int PL>
-__device__ __forceinline__ void wave_merge(uint64_t (&v)[PL], int lane)
-{
-    wstrides<PL, 0, kWave * PL / 2>(v, lane);
-}
-
 // Selection state of the wavefront's current query: its K = 64 * KPL best
 // keys in the blocked layout, and an LDS buffer of B = 64 * BPL keys that
 // candidates below the threshold are appended to.  A query asking for
@@ -163,7 +88,7 @@ struct WaveSel {
             const uint32_t s = (uint32_t)(lane * BPL + r);
             b[r] = s < cnt ? (uint64_t)buf[s] : kKeyMax;
         }
-        wave_sort<BPL>(b, lane);
+        net_sort<BPL, kWave * BPL>(b, lane);
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < BPL; ++r) buf[lane * BPL + r] = b[r];
@@ -173,7 +98,7 @@ struct WaveSel {
         // of both, which the merge network sorts.
 #pragma unroll
         for (int r = 0; r < KPL; ++r) a[r] = key_min(a[r], (uint64_t)buf[K - 1 - (lane * KPL + r)]);
-        wave_merge<KPL>(a, lane);
+        net_merge<KPL, kWave * KPL>(a, lane);
         __syncthreads();  // buffer reads done before new keys are appended
         cnt = 0;
         ++merges;

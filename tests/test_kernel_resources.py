@@ -30,7 +30,7 @@ def kernel_descriptors(src, tmp_path):
     return kds
 
 
-@pytest.mark.parametrize("name", ["index.hip", "query.hip", "query_wave.hip"])
+@pytest.mark.parametrize("name", ["index.hip", "query.hip", "query_wave.hip", "query_group.hip"])
 def test_no_scratch(name, tmp_path):
     kds = kernel_descriptors(os.path.join(build.HERE, "csrc", name), tmp_path)
     assert kds, "no kernels found"
@@ -41,7 +41,17 @@ def test_no_scratch(name, tmp_path):
 def test_query_kernel_register_budget(tmp_path):
     kds = kernel_descriptors(os.path.join(build.HERE, "csrc", "query.hip"), tmp_path)
     knn = {k: v for k, v in kds.items() if "k_knn_tiles" in k}
-    assert len(knn) == 5
+    assert len(knn) == 10  # five list sizes, with and without free centres
     # K = 32 (the benchmark's k) must keep 4 wavefronts per SIMD.
-    k32 = [v for k, v in knn.items() if "ILi32ELi16E" in k][0]
-    assert k32["vgpr"] <= 128, k32
+    for k32 in [v for k, v in knn.items() if "ILi32ELi16E" in k]:
+        assert k32["vgpr"] <= 128, k32
+
+
+def test_group_kernel_register_budget(tmp_path):
+    kds = kernel_descriptors(os.path.join(build.HERE, "csrc", "query_group.hip"), tmp_path)
+    grp = {k: v for k, v in kds.items() if "k_knn_group" in k}
+    assert len(grp) == 12  # groups of 2 to 64 lanes, with and without free centres
+    # Lists spread 16 keys per lane keep at least 3 wavefronts per SIMD
+    # (the lane flavour holds 2 at k = 64 and 1 at k = 128).
+    for k, v in grp.items():
+        assert v["vgpr"] <= 168, (k, v)
