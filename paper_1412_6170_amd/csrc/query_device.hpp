@@ -188,7 +188,11 @@ __device__ __forceinline__ void wstage_one(uint64_t (&v)[PL], int idx)
         constexpr int M = STRIDE / PL;
         const uint64_t w = shfl_xor_key(v[R], M);
         const bool lower = (idx & M) == 0;
-        v[R] = (lower == asc) ? key_min(v[R], w) : key_max(v[R], w);
+        // Both results, then a select: a choice between the two asm
+        // statements would be compiled as a branch around each.
+        const uint64_t lo = key_min(v[R], w);
+        const uint64_t hi = key_max(v[R], w);
+        v[R] = (lower == asc) ? lo : hi;
     }
 }
 

@@ -53,8 +53,12 @@ __device__ __forceinline__ void merge_runs(uint64_t (&b)[PL], int r)
         for (int s = 0; s < PL / 2; ++s) {
             const uint64_t w1 = shfl_xor_key(b[PL - 1 - s], 2 * H - 1);
             const uint64_t w2 = shfl_xor_key(b[s], 2 * H - 1);
-            b[s] = lower ? key_min(b[s], w1) : key_max(b[s], w1);
-            b[PL - 1 - s] = lower ? key_min(b[PL - 1 - s], w2) : key_max(b[PL - 1 - s], w2);
+            // Both results, then a select (a choice between two asm
+            // statements compiles to a branch around each).
+            const uint64_t lo1 = key_min(b[s], w1), hi1 = key_max(b[s], w1);
+            const uint64_t lo2 = key_min(b[PL - 1 - s], w2), hi2 = key_max(b[PL - 1 - s], w2);
+            b[s] = lower ? lo1 : hi1;
+            b[PL - 1 - s] = lower ? lo2 : hi2;
         }
         net_merge<PL, H * PL>(b, r);
         merge_runs<PL, 2 * H, G>(b, r);
