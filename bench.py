@@ -66,12 +66,12 @@ CPU_SAMPLE_SECONDS = 10.0
 # taken on (digest of the query kernel's sources without comments);
 # otherwise the roofline's traffic is null.
 MEASURED_TRAFFIC = [
-    {"digest": "7fa74b1daa904dd6", "workload": "clustered_1m", "leaf_capacity": 48, "max_level": 14,
-     "fetch_bytes": 45924227, "write_bytes": 290679984, "valu_insts": 171914364},
-    {"digest": "7fa74b1daa904dd6", "workload": "clustered_1m", "leaf_capacity": 48, "max_level": 12,
-     "fetch_bytes": 45486473, "write_bytes": 290661104, "valu_insts": 172972986},
-    {"digest": "7fa74b1daa904dd6", "workload": "clustered_1m", "leaf_capacity": 64, "max_level": 12,
-     "fetch_bytes": 40947351, "write_bytes": 290677568, "valu_insts": 183013442},
+    {"digest": "0329ab863fcb7aed", "workload": "clustered_1m", "leaf_capacity": 48, "max_level": 14,
+     "fetch_bytes": 45926562, "write_bytes": 290670288, "valu_insts": 171914364},
+    {"digest": "0329ab863fcb7aed", "workload": "clustered_1m", "leaf_capacity": 48, "max_level": 12,
+     "fetch_bytes": 45490057, "write_bytes": 290699192, "valu_insts": 172972986},
+    {"digest": "0329ab863fcb7aed", "workload": "clustered_1m", "leaf_capacity": 64, "max_level": 12,
+     "fetch_bytes": 41055118, "write_bytes": 290666584, "valu_insts": 183013442},
 ]
 
 
