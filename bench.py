@@ -166,6 +166,9 @@ def roofline_entry(workload, leaf_capacity, max_level, k, kern_ms, kern_bytes, s
     if sweep == "wave":
         kclass = max(64, 1 << (max(k, 1) - 1).bit_length())
         name = "k_knn_wave (one query per wavefront), list of %d keys" % kclass
+    elif sweep == "group":
+        kclass = max(32, 1 << (max(k, 1) - 1).bit_length())
+        name = "k_knn_group (one query per %d lanes), list of %d keys" % (kclass // 16, kclass)
     else:
         kclass = 8 if k <= 8 else 16 if k <= 16 else 32 if k <= 32 else 64 if k <= 64 else 128
         name = "k_knn_tiles (one query per lane), k class %d" % kclass
