@@ -269,18 +269,20 @@ struct Lane {
 
     // A node is needed if its box may hold a key below some lane's
     // threshold (queued keys are not yet counted, so this errs on the side
-    // of visiting).
+    // of visiting).  A lane without a query has a zero threshold and the
+    // centre of the launch's last query, which is in the same wavefront: it
+    // wants a node only if that box contains the centre, and then so does
+    // the lane of that query, so it adds no visit and needs no test of its
+    // own.
     __device__ __forceinline__ bool wants(const Node &nd) const
     {
-        return active &&
-               __float_as_uint(box_lower_bound(qx, qy, nd, pad)) <= (uint32_t)(sel.thr >> 32);
+        return __float_as_uint(box_lower_bound(qx, qy, nd, pad)) <= (uint32_t)(sel.thr >> 32);
     }
     // The same with unpadded boxes (right after a full build): x - 0 = x, so
     // the bound is identical, with four fewer operations.
     __device__ __forceinline__ bool wants_exact(const Node &nd) const
     {
-        return active &&
-               __float_as_uint(box_lower_bound_exact(qx, qy, nd)) <= (uint32_t)(sel.thr >> 32);
+        return __float_as_uint(box_lower_bound_exact(qx, qy, nd)) <= (uint32_t)(sel.thr >> 32);
     }
 };
 

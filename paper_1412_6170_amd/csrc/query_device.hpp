@@ -53,10 +53,22 @@ __device__ __forceinline__ float sq_dist(float qx, float qy, float px, float py)
     return ax + ay;
 }
 
+// Gap between a coordinate and the interval [lo, hi): lo - v below it,
+// v - hi at or above hi, zero inside.  Exactly one of the two differences
+// can be positive (lo < hi), so the largest of them and zero is that gap,
+// computed without a branch.
+__device__ __forceinline__ float interval_gap(float v, float lo, float hi)
+{
+    return fmaxf(fmaxf(lo - v, v - hi), 0.0f);
+}
+
+// Lower bound of d2 over the node's box.  Every object of the box lies on
+// the far side of the gap's edge, and rounding is monotone, so its rounded
+// squared distance is no smaller.
 __device__ __forceinline__ float box_lower_bound_exact(float qx, float qy, const Node &nd)
 {
-    const float gx = (qx < nd.x0) ? (nd.x0 - qx) : ((qx >= nd.x1) ? (qx - nd.x1) : 0.0f);
-    const float gy = (qy < nd.y0) ? (nd.y0 - qy) : ((qy >= nd.y1) ? (qy - nd.y1) : 0.0f);
+    const float gx = interval_gap(qx, nd.x0, nd.x1);
+    const float gy = interval_gap(qy, nd.y0, nd.y1);
     const float ax = gx * gx;
     const float ay = gy * gy;
     return ax + ay;
@@ -66,10 +78,8 @@ __device__ __forceinline__ float box_lower_bound_exact(float qx, float qy, const
 // right after a full build; after refit ticks it covers the objects' drift).
 __device__ __forceinline__ float box_lower_bound(float qx, float qy, const Node &nd, float pad)
 {
-    const float x0 = nd.x0 - pad, x1 = nd.x1 + pad;
-    const float y0 = nd.y0 - pad, y1 = nd.y1 + pad;
-    const float gx = (qx < x0) ? (x0 - qx) : ((qx >= x1) ? (qx - x1) : 0.0f);
-    const float gy = (qy < y0) ? (y0 - qy) : ((qy >= y1) ? (qy - y1) : 0.0f);
+    const float gx = interval_gap(qx, nd.x0 - pad, nd.x1 + pad);
+    const float gy = interval_gap(qy, nd.y0 - pad, nd.y1 + pad);
     const float ax = gx * gx;
     const float ay = gy * gy;
     return ax + ay;

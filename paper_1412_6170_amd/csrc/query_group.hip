@@ -170,11 +170,14 @@ struct GroupQuery {
         }
     }
 
+    // Groups without a query have a zero threshold and the centre of the
+    // launch's last query, whose group is in the same wavefront, so they
+    // add no visit (see the lane flavour) and are not tested apart.
     __device__ __forceinline__ bool wants(const Node &nd) const
     {
         const float lb = pad == 0.0f ? box_lower_bound_exact(qx, qy, nd)
                                      : box_lower_bound(qx, qy, nd, pad);
-        return active && __float_as_uint(lb) <= (uint32_t)(thr >> 32);
+        return __float_as_uint(lb) <= (uint32_t)(thr >> 32);
     }
 
     // The next leaf of the table from pos that some lane wants is swept;
