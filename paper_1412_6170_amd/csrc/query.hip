@@ -128,9 +128,11 @@ __device__ __forceinline__ void bitonic_merge(uint64_t (&a)[N])
 // centre may exclude any object, so then every merge masks it by id.
 template <int K, int P>
 struct Selector {
+    static constexpr uint32_t kSlotBytes = kWave * sizeof(uint64_t);  // slot stride
     uint64_t a[K];
     lds_u64 *q;        // this lane's queue: q[s * kWave], s < P
-    uint32_t cnt;
+    uint32_t q0;       // LDS byte address of slot 0 (that of q)
+    uint32_t qnext;    // LDS byte address of the next free slot
     uint64_t cap;      // exclusive upper bound of the keys the lane takes
     uint64_t thr;      // min(a[K-1], cap) at the last merge
     uint32_t excl;     // id of the excluded object (the issuer), or kNoExclude
@@ -140,7 +142,8 @@ struct Selector {
 #pragma unroll
         for (int s = 0; s < K; ++s) a[s] = (s < K - k) ? 0ull : kKeyMax;
         q = lane_queue;
-        cnt = 0;
+        q0 = (uint32_t)(uintptr_t)lane_queue;
+        qnext = q0;
         cap = kKeyMax;
         thr = kKeyMax;
         excl = excl_id;
@@ -152,26 +155,46 @@ struct Selector {
         thr = key_min(a[K - 1], cap);
     }
 
+    // Keys in the queue.
+    __device__ __forceinline__ uint32_t count() const { return (qnext - q0) / kSlotBytes; }
+    // Whether the queue holds more than m keys.
+    __device__ __forceinline__ bool holds_more_than(uint32_t m) const
+    {
+        return qnext > q0 + m * kSlotBytes;
+    }
+
     // Every lane writes its key to its next free slot; only lanes whose key
     // passes advance.  No branch, so no lane waits on another's insertion.
+    // The slot is tracked by its address, so a write needs no address
+    // arithmetic.
     __device__ __forceinline__ void offer(uint64_t key)
     {
-        q[cnt * kWave] = key;
-        cnt += key_less(key, thr) ? 1u : 0u;
+        *(lds_u64 *)(uintptr_t)qnext = key;
+        qnext += key_less(key, thr) ? kSlotBytes : 0u;
     }
 
     template <bool MASK_EXCL>
     __device__ __forceinline__ void merge()
     {
         // Read every slot (volatile keeps the loads unconditional: slots
-        // past cnt hold stale keys and are masked after the load).
+        // past the count hold stale keys).  A stale or excluded key gets the
+        // high word of the largest key and keeps its low word: it then lies
+        // above every key of a real distance (whose high word is at most
+        // that of +inf), so it can only take the place of a largest-key
+        // filler of the list, which it equals in every use (threshold,
+        // pruning, output; see kFillHi).  One select per slot instead of two.
         const volatile lds_u64 *vq = q;
+        const uint32_t cnt = count();
         uint64_t b[P];
 #pragma unroll
         for (int s = 0; s < P; ++s) b[s] = vq[s * kWave];
 #pragma unroll
-        for (int s = 0; s < P; ++s)
-            b[s] = ((uint32_t)s < cnt && (!MASK_EXCL || (uint32_t)b[s] != excl)) ? b[s] : kKeyMax;
+        for (int s = 0; s < P; ++s) {
+            const uint32_t lo = (uint32_t)b[s];
+            const bool keep = (uint32_t)s < cnt && (!MASK_EXCL || lo != excl);
+            const uint32_t hi = keep ? (uint32_t)(b[s] >> 32) : kFillHi;
+            b[s] = ((uint64_t)hi << 32) | lo;
+        }
         oddeven_sort<P>(b);
 #pragma unroll
         for (int i = K - P; i < K; ++i) a[i] = key_min(a[i], b[K - 1 - i]);
@@ -191,7 +214,7 @@ struct Selector {
         } else {
             bitonic_merge<K>(a);
         }
-        cnt = 0;
+        qnext = q0;
         thr = key_min(a[K - 1], cap);
     }
 };
@@ -257,12 +280,12 @@ struct Lane {
                 const Point p0 = stage[j], p1 = stage[j + 1];
                 offer<CHECK>(p0);
                 offer<CHECK>(p1);
-                merge_if(sel.cnt > (uint32_t)(P - 2));
+                merge_if(sel.holds_more_than(P - 2));
             }
             if (j < m) {
                 const Point p0 = stage[j];
                 offer<CHECK>(p0);
-                merge_if(sel.cnt > (uint32_t)(P - 2));
+                merge_if(sel.holds_more_than(P - 2));
             }
         }
     }
@@ -414,7 +437,7 @@ __global__ __launch_bounds__(kWave) void k_knn_tiles(QueryArgs qa)
         right = !right;
     }
 
-    if (wave_any(ln.sel.cnt > 0)) {
+    if (wave_any(ln.sel.holds_more_than(0))) {
         ln.sel.template merge<FREE>();
         ++ln.n_merge;
     }
@@ -444,7 +467,7 @@ __global__ __launch_bounds__(kWave) void k_knn_tiles(QueryArgs qa)
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const uint64_t v = ln.sel.a[s + u];
-                const bool real = v != kKeyMax;
+                const bool real = (uint32_t)(v >> 32) < kFillHi;
                 pi[u] = real ? (int32_t)(uint32_t)v : -1;
                 pd[u] = real ? __uint_as_float((uint32_t)(v >> 32)) : __builtin_inff();
                 cnt += real ? 1 : 0;
@@ -458,7 +481,7 @@ __global__ __launch_bounds__(kWave) void k_knn_tiles(QueryArgs qa)
             const int slot = s - (K - kq);
             if (slot >= 0) {
                 const uint64_t v = ln.sel.a[s];
-                const bool real = v != kKeyMax;
+                const bool real = (uint32_t)(v >> 32) < kFillHi;
                 oi[slot] = real ? (int32_t)(uint32_t)v : -1;
                 od[slot] = real ? __uint_as_float((uint32_t)(v >> 32)) : __builtin_inff();
                 cnt += real ? 1 : 0;

@@ -20,6 +20,10 @@ namespace mknn {
 // one fp64 max.  The empty-slot key is the largest finite double, above
 // every real key (whose high word is at most 0x7f7fffff).
 constexpr uint64_t kKeyMax = 0x7fefffffffffffffull;
+// High word of kKeyMax.  Any key with this high word is a filler, not a
+// neighbour, whatever its low word: it lies above every real key and at or
+// below kKeyMax, so as a threshold or a pruning bound it admits everything.
+constexpr uint32_t kFillHi = 0x7fefffffu;
 
 __device__ __forceinline__ double as_f64(uint64_t k) { return __longlong_as_double((long long)k); }
 __device__ __forceinline__ uint64_t as_key(double d) { return (uint64_t)__double_as_longlong(d); }

@@ -72,7 +72,9 @@ struct GroupQuery {
 
     uint64_t a[PL];    // this lane's part of the list
     lds_u64 *q;        // this lane's queue: q[s * kWave], s < PL
-    uint32_t cnt;      // keys in this lane's queue
+    static constexpr uint32_t kSlotBytes = kWave * sizeof(uint64_t);  // slot stride
+    uint32_t q0;       // LDS byte address of slot 0 (that of q)
+    uint32_t qnext;    // LDS byte address of this lane's next free slot
     uint64_t cap;      // zero for lanes without a query, else the largest key
     uint64_t thr;      // min(the list's last key, cap) at the last merge
     uint32_t excl;     // the excluded object, or kNoExclude
@@ -90,18 +92,25 @@ struct GroupQuery {
 #pragma unroll
         for (int s = 0; s < PL; ++s) a[s] = (r * PL + s < K - k) ? 0ull : kKeyMax;
         q = lane_queue;
-        cnt = 0;
+        q0 = (uint32_t)(uintptr_t)lane_queue;
+        qnext = q0;
         active = has_query;
         cap = has_query ? kKeyMax : 0ull;
         thr = cap;
         excl = excl_id;
     }
 
+    __device__ __forceinline__ uint32_t count() const { return (qnext - q0) / kSlotBytes; }
+    __device__ __forceinline__ bool holds_more_than(uint32_t m) const
+    {
+        return qnext > q0 + m * kSlotBytes;
+    }
+
     // One candidate: written to the next free slot, counted if it passes.
     __device__ __forceinline__ void offer(uint64_t key)
     {
-        q[cnt * kWave] = key;
-        cnt += key_less(key, thr) ? 1u : 0u;
+        *(lds_u64 *)(uintptr_t)qnext = key;
+        qnext += key_less(key, thr) ? kSlotBytes : 0u;
     }
 
     __device__ __forceinline__ void merge()
@@ -110,9 +119,16 @@ struct GroupQuery {
         uint64_t b[PL];
 #pragma unroll
         for (int s = 0; s < PL; ++s) b[s] = vq[s * kWave];
+        // Stale and excluded keys get the filler high word (as in the lane
+        // flavour's merge).
+        const uint32_t cnt = count();
 #pragma unroll
-        for (int s = 0; s < PL; ++s)
-            b[s] = ((uint32_t)s < cnt && (!FREE || (uint32_t)b[s] != excl)) ? b[s] : kKeyMax;
+        for (int s = 0; s < PL; ++s) {
+            const uint32_t lo = (uint32_t)b[s];
+            const bool keep = (uint32_t)s < cnt && (!FREE || lo != excl);
+            const uint32_t hi = keep ? (uint32_t)(b[s] >> 32) : kFillHi;
+            b[s] = ((uint64_t)hi << 32) | lo;
+        }
         // The group's queued keys, sorted over the group: each lane's run,
         // then the runs merged.
         oddeven_sort<PL>(b);
@@ -122,7 +138,7 @@ struct GroupQuery {
 #pragma unroll
         for (int s = 0; s < PL; ++s) a[s] = key_min(a[s], shfl_xor_key(b[PL - 1 - s], G - 1));
         net_merge<PL, K>(a, r);
-        cnt = 0;
+        qnext = q0;
         thr = key_min(shfl_key(a[PL - 1], last_lane), cap);
     }
 
@@ -165,7 +181,7 @@ struct GroupQuery {
                 hi = i < m ? hi : 0x7ff00000u;
                 if constexpr (CHECK) hi = p.id == excl ? 0x7ff00000u : hi;
                 offer(((uint64_t)hi << 32) | p.id);
-                merge_if(cnt > (uint32_t)(PL - 1));
+                merge_if(holds_more_than(PL - 1));
             }
         }
     }
@@ -285,7 +301,7 @@ __global__ __launch_bounds__(kWave) void k_knn_group(QueryArgs qa)
         rl = fw ? rl : pos;
         right = !right;
     }
-    if (wave_any(w.cnt > 0)) {
+    if (wave_any(w.holds_more_than(0))) {
         w.merge();
         ++w.n_merge;
     }
@@ -315,7 +331,7 @@ __global__ __launch_bounds__(kWave) void k_knn_group(QueryArgs qa)
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const uint64_t v = w.a[s + u];
-                    const bool real = v != kKeyMax;
+                    const bool real = (uint32_t)(v >> 32) < kFillHi;
                     pi[u] = real ? (int32_t)(uint32_t)v : -1;
                     pd[u] = real ? __uint_as_float((uint32_t)(v >> 32)) : __builtin_inff();
                     cnt += real ? 1 : 0;
@@ -329,7 +345,7 @@ __global__ __launch_bounds__(kWave) void k_knn_group(QueryArgs qa)
                 const int slot = first + s;
                 if (slot >= 0) {
                     const uint64_t v = w.a[s];
-                    const bool real = v != kKeyMax;
+                    const bool real = (uint32_t)(v >> 32) < kFillHi;
                     oi[slot] = real ? (int32_t)(uint32_t)v : -1;
                     od[slot] = real ? __uint_as_float((uint32_t)(v >> 32)) : __builtin_inff();
                     cnt += real ? 1 : 0;
