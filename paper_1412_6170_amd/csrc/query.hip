@@ -126,6 +126,9 @@ __device__ __forceinline__ void bitonic_merge(uint64_t (&a)[N])
 // the list: an issuer lies in its own leaf, so it is met only in the first
 // sweep, whose candidates are checked by id as they are offered; a free
 // centre may exclude any object, so then every merge masks it by id.
+// Largest list filled straight from the own leaves (fill below).
+constexpr int kFillMaxK = 64;
+
 template <int K, int P>
 struct Selector {
     static constexpr uint32_t kSlotBytes = kWave * sizeof(uint64_t);  // slot stride
@@ -247,6 +250,43 @@ struct Lane {
             sel.template merge<FREE>();
             ++n_merge;
         }
+    }
+
+    // The list starts from the keys of the first K objects of the own
+    // leaves [b, b + K), sorted (K <= kWave: one staged chunk).  With an
+    // empty list every key passes, so queueing those objects would fill
+    // every queue in a few steps and cost several merges.  The excluded
+    // object gets a filler key.  Lanes asking for kq < K keep their K - kq
+    // zero sentinels: the kq smallest keys go above them in reverse order,
+    // which leaves a bitonic sequence for a bitonic merge to sort.
+    __device__ __forceinline__ void fill(const Point *__restrict__ pts, int32_t b, int kq,
+                                         Point *stage)
+    {
+        static_assert(K <= kWave, "one staged chunk");
+        const int lane = threadIdx.x & (kWave - 1);
+        reinterpret_cast<uint4 *>(stage)[lane] =
+            reinterpret_cast<const uint4 *>(pts)[b + min(lane, K - 1)];
+        uint64_t (&a)[K] = sel.a;
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+            const Point p = stage[s];
+            const float d2 = sq_dist(qx, qy, p.x, p.y);
+            const uint32_t hi = p.id == sel.excl ? kFillHi : __float_as_uint(d2);
+            a[s] = ((uint64_t)hi << 32) | p.id;
+        }
+        oddeven_sort<K>(a);
+        if (wave_any(kq < K)) {
+            const int z = K - kq;  // sentinels
+#pragma unroll
+            for (int s = 0; s < K / 2; ++s) {
+                const uint64_t lo = a[s], hi = a[K - 1 - s];
+                a[s] = s < z ? 0ull : hi;
+                a[K - 1 - s] = K - 1 - s < z ? 0ull : lo;
+            }
+            bitonic_merge<K>(a);
+        }
+        sel.thr = key_min(a[K - 1], sel.cap);
+        n_cand += K;
     }
 
     // Every lane evaluates every object of the sorted range [b, e).  The
@@ -414,9 +454,17 @@ __global__ __launch_bounds__(kWave) void k_knn_tiles(QueryArgs qa)
     l0 = __builtin_amdgcn_readfirstlane(l0);
     l1 = __builtin_amdgcn_readfirstlane(l1);
 
-    // First iteration: the own leaves.
-    ln.template sweep<true>(qa.pts, max(qa.leaf_begin[l0], 0), min(qa.leaf_end[l1], (int32_t)qa.n),
-                            stage);
+    // First iteration: the own leaves (their first K objects straight into
+    // the list when there are enough of them).
+    int32_t own_b = max(qa.leaf_begin[l0], 0);
+    const int32_t own_e = min(qa.leaf_end[l1], (int32_t)qa.n);
+    if constexpr (K <= kFillMaxK) {
+        if (own_e - own_b >= K) {
+            ln.fill(qa.pts, own_b, kq, stage);
+            own_b += K;
+        }
+    }
+    ln.template sweep<true>(qa.pts, own_b, own_e, stage);
 
     // Subsequent iterations: alternate the two sub-visits.
     const int32_t total = min((int32_t)qa.ctr->n_nodes, qa.node_cap);
