@@ -53,7 +53,7 @@ SCHEDULE_SPACE = {"leaf_capacity": TH_CANDIDATES, "max_level": (12, 14, 16),
 TUNED_SCHEDULE = {
     "uniform_10k": {"leaf_capacity": 32, "max_level": 16, "sweep": "lane", "group_k": False},
     "clustered_1m": {"leaf_capacity": 48, "max_level": 14, "sweep": "lane", "group_k": False},
-    "network_4m": {"leaf_capacity": 64, "max_level": 12, "sweep": "lane", "group_k": False},
+    "network_4m": {"leaf_capacity": 64, "max_level": 12, "sweep": "group", "group_k": False},
     "mixed_16m": {"leaf_capacity": 64, "max_level": 16, "sweep": "group", "group_k": False},
 }
 CPU_SAMPLE_SECONDS = 10.0

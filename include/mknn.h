@@ -86,7 +86,7 @@ extern "C" {
  * power of two, at least 2): its list spread 16 keys per lane over the
  * group, 64 / group queries per wavefront sharing their candidates, lists
  * merged by bitonic networks across the group's lanes (any k up to
- * MKNN_K_LIMIT).  AUTO takes LANE up to k = 64 and GROUP above; LANE
+ * MKNN_K_LIMIT).  AUTO takes LANE up to k = 32 and GROUP above; LANE
  * itself hands k above 128 to WAVE.  Results are the same in every
  * flavour. */
 #define MKNN_SWEEP_AUTO 0

@@ -326,14 +326,19 @@ int mark_main(mknn_ctx *c, bool prepared)
 
 // The flavour a query runs with: the schedule's, except that the lane
 // flavour hands lists above its 128 keys to the one-query-per-wavefront
-// flavour.  AUTO takes one query per lane up to k = 64 and a group of lanes
-// per query above, where a lane-private list would leave at most two
-// wavefronts per SIMD (k = 128 on mixed_16m: 36 ms per query kernel
-// against 45 ms).
+// flavour.  AUTO takes one query per lane up to k = 32 and a group of lanes
+// per query above: from k = 64 a lane-private list leaves at most two
+// wavefronts per SIMD (query kernel at the 64-key class on network_4m:
+// 1.06 ms grouped against 1.26 ms; k = 128 on mixed_16m: 24 ms against
+// 45 ms), while at k = 32 one lane per query wins (0.37 against 0.45 ms on
+// clustered_1m).
+constexpr int kAutoLaneMaxK = 32;
+
 int sweep_flavour(const mknn_ctx *c, int kmax_call)
 {
     if (c->sweep == MKNN_SWEEP_GROUP || c->sweep == MKNN_SWEEP_WAVE) return c->sweep;
-    if (c->sweep == MKNN_SWEEP_AUTO) return kmax_call > 64 ? MKNN_SWEEP_GROUP : MKNN_SWEEP_LANE;
+    if (c->sweep == MKNN_SWEEP_AUTO)
+        return kmax_call > kAutoLaneMaxK ? MKNN_SWEEP_GROUP : MKNN_SWEEP_LANE;
     return kmax_call > 128 ? MKNN_SWEEP_WAVE : MKNN_SWEEP_LANE;
 }
 

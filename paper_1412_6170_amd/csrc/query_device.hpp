@@ -159,6 +159,41 @@ __device__ __forceinline__ uint64_t shfl_xor_key(uint64_t v, int m)
     return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
 }
 
+// The value of lane (lane ^ M), M a compile-time mask.  Patterns that stay
+// inside a row of 16 lanes are DPP moves, one VALU instruction per dword
+// with no trip through the LDS unit: quad permutes for 1, 2 and 3, the
+// half-row and row mirrors for 7 and 15, a row rotation by 8 for 8, and for
+// 4 two row shifts each writing the half of the lanes (banks of 4 lanes)
+// it serves.  Other masks use the LDS permute.
+template <int M>
+__device__ __forceinline__ uint32_t xor_dword(uint32_t x)
+{
+    const int v = (int)x;
+    // DPP controls: quad_perm [1,0,3,2] [2,3,0,1] [3,2,1,0]; row_half_mirror;
+    // row_mirror; row_ror:8; row_shl:4 (lane i reads i + 4) into banks 0
+    // and 2, row_shr:4 (reads i - 4) into banks 1 and 3.
+    if constexpr (M == 1) return (uint32_t)__builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);
+    else if constexpr (M == 2) return (uint32_t)__builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);
+    else if constexpr (M == 3) return (uint32_t)__builtin_amdgcn_mov_dpp(v, 0x1B, 0xF, 0xF, false);
+    else if constexpr (M == 7) return (uint32_t)__builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false);
+    else if constexpr (M == 15) return (uint32_t)__builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, false);
+    else if constexpr (M == 8) return (uint32_t)__builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, false);
+    else if constexpr (M == 4) {
+        const int t = __builtin_amdgcn_mov_dpp(v, 0x104, 0xF, 0x5, false);
+        return (uint32_t)__builtin_amdgcn_update_dpp(t, v, 0x114, 0xF, 0xA, false);
+    } else {
+        return (uint32_t)__shfl_xor(v, M, kWave);
+    }
+}
+
+template <int M>
+__device__ __forceinline__ uint64_t xor_key(uint64_t v)
+{
+    const uint32_t lo = xor_dword<M>((uint32_t)v);
+    const uint32_t hi = xor_dword<M>((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
 __device__ __forceinline__ uint64_t shfl_key(uint64_t v, int src)
 {
     const int lo = __shfl((int)(uint32_t)v, src, kWave);
@@ -200,7 +235,7 @@ __device__ __forceinline__ void wstage_one(uint64_t (&v)[PL], int idx)
         }
     } else {
         constexpr int M = STRIDE / PL;
-        const uint64_t w = shfl_xor_key(v[R], M);
+        const uint64_t w = xor_key<M>(v[R]);
         const bool lower = (idx & M) == 0;
         // Both results, then a select: a choice between the two asm
         // statements would be compiled as a branch around each.

@@ -51,8 +51,8 @@ __device__ __forceinline__ void merge_runs(uint64_t (&b)[PL], int r)
         const bool lower = (r & H) == 0;
 #pragma unroll
         for (int s = 0; s < PL / 2; ++s) {
-            const uint64_t w1 = shfl_xor_key(b[PL - 1 - s], 2 * H - 1);
-            const uint64_t w2 = shfl_xor_key(b[s], 2 * H - 1);
+            const uint64_t w1 = xor_key<2 * H - 1>(b[PL - 1 - s]);
+            const uint64_t w2 = xor_key<2 * H - 1>(b[s]);
             // Both results, then a select (a choice between two asm
             // statements compiles to a branch around each).
             const uint64_t lo1 = key_min(b[s], w1), hi1 = key_max(b[s], w1);
@@ -136,7 +136,7 @@ struct GroupQuery {
         // Key i of the list against key K-1-i of the sorted queue, which sits
         // in the mirrored lane of the group, mirrored register.
 #pragma unroll
-        for (int s = 0; s < PL; ++s) a[s] = key_min(a[s], shfl_xor_key(b[PL - 1 - s], G - 1));
+        for (int s = 0; s < PL; ++s) a[s] = key_min(a[s], xor_key<G - 1>(b[PL - 1 - s]));
         net_merge<PL, K>(a, r);
         qnext = q0;
         thr = key_min(shfl_key(a[PL - 1], last_lane), cap);
