@@ -72,16 +72,21 @@ __device__ __forceinline__ uint32_t quadrant_of(uint32_t code, int l)
     return l <= 0 ? 0u : code >> (2 * (kCodeLevels - l));
 }
 
-// Inclusive scan across one wavefront.
+// Inclusive scan across one wavefront, with DPP adds that stay in the
+// vector unit: shifts by 1, 2, 4 and 8 lanes inside each row of 16 (lanes
+// whose source falls outside the row add zero), then the last lane of row
+// 0 and of row 2 added to rows 1 and 3, then lane 31 added to rows 2 and 3.
+// Every lane of the wavefront must be active.
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
 {
-    const int lane = threadIdx.x & (kWave - 1);
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        uint32_t t = __shfl_up(v, d, kWave);
-        if (lane >= d) v += t;
-    }
-    return v;
+    int x = (int)v;
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xF, 0xF, true);   // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xF, 0xF, true);   // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xF, 0xF, true);   // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xF, 0xF, true);   // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false);  // row_bcast:15
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false);  // row_bcast:31
+    return (uint32_t)x;
 }
 
 // Exclusive scan across a workgroup of NT threads; *total gets the sum.
