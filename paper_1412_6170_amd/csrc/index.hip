@@ -434,6 +434,13 @@ __global__ __launch_bounds__(NT) void k_radix_pass(
     const bool digit_thread = t < kRadixBins;  // thread t < 256 owns digit t
     for (int i = t; i < NW * kRadixBins; i += NT) (&s_wc[0][0])[i] = 0;
     const uint32_t tile = take_ticket(ticket);  // also orders the clearing above
+    // This pass's count of digit t over all keys (the copies summed),
+    // fetched now so the loads overlap the ranking.
+    uint32_t digit_total = 0;
+    if (digit_thread) {
+#pragma unroll
+        for (int c = 0; c < kGhistCopies; ++c) digit_total += ghist[c * kGhistStride + t];
+    }
     const uint32_t base = tile * (uint32_t)TILE;
     const uint32_t n_valid = min((uint32_t)TILE, n - base);
     const uint64_t lt_mask = (1ull << lane) - 1ull;
@@ -496,12 +503,7 @@ __global__ __launch_bounds__(NT) void k_radix_pass(
     // their own, so the waits of the look-back, which count that wave's
     // memory reads in order, do not wait for them too.
     {
-        uint32_t count = 0;
-        if (digit_thread) {
-#pragma unroll
-            for (int c = 0; c < kGhistCopies; ++c) count += ghist[c * kGhistStride + t];
-        }
-        const uint32_t below = block_excl_scan<NT>(count, nullptr);
+        const uint32_t below = block_excl_scan<NT>(digit_total, nullptr);
         if (digit_thread) {
             const uint64_t before = lb_resolve(status + t, kRadixBins, tile, real, err, epoch);
             s_base[t] = below + (uint32_t)before;

@@ -89,10 +89,12 @@ def test_create_takes_the_reported_footprint():
     say("api: footprint %d B, create took %d B, destroy gave back %d B" % (fp, taken, given_back))
     # Large buffers are mapped in whole 2 MiB pages, which the footprint
     # counts; the few small ones may come from memory the runtime holds.
-    slack = 4 << 20
-    assert fp - slack <= taken <= fp + slack
-    # The runtime may keep a few MiB mapped after the buffers are freed.
-    assert given_back >= taken - (16 << 20)
+    # The runtime may keep a few MiB mapped after buffers are freed (by
+    # earlier tests of the same process, or by this one), and a later
+    # create can take its buffers from there.
+    held = 16 << 20
+    assert fp - held <= taken <= fp + (4 << 20)
+    assert given_back >= taken - held
 
 
 def test_readme_python_example():
