@@ -53,7 +53,7 @@ SCHEDULE_SPACE = {"leaf_capacity": TH_CANDIDATES, "max_level": (12, 14, 16),
 TUNED_SCHEDULE = {
     "uniform_10k": {"leaf_capacity": 32, "max_level": 16, "sweep": "lane", "group_k": False},
     "clustered_1m": {"leaf_capacity": 48, "max_level": 14, "sweep": "lane", "group_k": False},
-    "network_4m": {"leaf_capacity": 64, "max_level": 12, "sweep": "group", "group_k": False},
+    "network_4m": {"leaf_capacity": 96, "max_level": 12, "sweep": "group", "group_k": False},
     "mixed_16m": {"leaf_capacity": 64, "max_level": 16, "sweep": "group", "group_k": False},
 }
 CPU_SAMPLE_SECONDS = 10.0
@@ -66,12 +66,12 @@ CPU_SAMPLE_SECONDS = 10.0
 # taken on (digest of the query kernel's sources without comments);
 # otherwise the roofline's traffic is null.
 MEASURED_TRAFFIC = [
-    {"digest": "0329ab863fcb7aed", "workload": "clustered_1m", "leaf_capacity": 48, "max_level": 14,
-     "fetch_bytes": 45926562, "write_bytes": 290670288, "valu_insts": 171914364},
-    {"digest": "0329ab863fcb7aed", "workload": "clustered_1m", "leaf_capacity": 48, "max_level": 12,
-     "fetch_bytes": 45490057, "write_bytes": 290699192, "valu_insts": 172972986},
-    {"digest": "0329ab863fcb7aed", "workload": "clustered_1m", "leaf_capacity": 64, "max_level": 12,
-     "fetch_bytes": 41055118, "write_bytes": 290666584, "valu_insts": 183013442},
+    {"digest": "b9114375deae7884", "workload": "clustered_1m", "leaf_capacity": 48, "max_level": 14,
+     "fetch_bytes": 44963607, "write_bytes": 290682448, "valu_insts": 151083674},
+    {"digest": "b9114375deae7884", "workload": "clustered_1m", "leaf_capacity": 48, "max_level": 12,
+     "fetch_bytes": 44579641, "write_bytes": 290688648, "valu_insts": 152106892},
+    {"digest": "b9114375deae7884", "workload": "clustered_1m", "leaf_capacity": 64, "max_level": 12,
+     "fetch_bytes": 40062693, "write_bytes": 290701432, "valu_insts": 162653896},
 ]
 
 
