@@ -150,6 +150,43 @@ struct GroupQuery {
         }
     }
 
+    // The list starts from the keys of the first K objects of the own
+    // leaves [b, b + K), sorted over the group, instead of from a first
+    // merge of queues that every key passes.  Lane r of a group reads
+    // objects s G + r (consecutive lanes, consecutive records).  The
+    // excluded object gets a filler key.  Groups asking for kq < K keep
+    // K - kq zero sentinels: the kq smallest keys go above them in reverse
+    // order (mirrored lane, mirrored register), and a bitonic merge over
+    // the group sorts the result.  (Starting from fewer objects, with
+    // fillers for the rest, measured slower: the threshold stays open and
+    // the first merge still comes.)
+    __device__ __forceinline__ void fill(const Point *__restrict__ pts, int32_t b, int kq)
+    {
+#pragma unroll
+        for (int s = 0; s < PL; ++s) {
+            const Point p = pts[b + s * G + r];
+            const float d2 = sq_dist(qx, qy, p.x, p.y);
+            const uint32_t hi = p.id == excl ? kFillHi : __float_as_uint(d2);
+            a[s] = ((uint64_t)hi << 32) | p.id;
+        }
+        oddeven_sort<PL>(a);
+        merge_runs<PL, 1, G>(a, r);
+        if (wave_any(kq < K)) {
+            const int z = K - kq;  // sentinels
+#pragma unroll
+            for (int s = 0; s < PL / 2; ++s) {
+                // Key K-1-i for i = r PL + s and for i = r PL + PL-1-s.
+                const uint64_t m1 = xor_key<G - 1>(a[PL - 1 - s]);
+                const uint64_t m2 = xor_key<G - 1>(a[s]);
+                a[s] = r * PL + s < z ? 0ull : m1;
+                a[PL - 1 - s] = r * PL + PL - 1 - s < z ? 0ull : m2;
+            }
+            net_merge<PL, K>(a, r);
+        }
+        thr = key_min(shfl_key(a[PL - 1], last_lane), cap);
+        n_cand += (uint32_t)K;
+    }
+
     // Every object of the sorted range [b, e): 64 records at a time staged in
     // LDS, G of them per step to every group (lane r of a group takes record
     // step * G + r).  Lanes past the range offer a key that passes no
@@ -283,8 +320,15 @@ __global__ __launch_bounds__(kWave) void k_knn_group(QueryArgs qa)
     }
     l0 = __builtin_amdgcn_readfirstlane(l0);
     l1 = __builtin_amdgcn_readfirstlane(l1);
-    w.template sweep<true>(qa.pts, max(qa.leaf_begin[l0], 0), min(qa.leaf_end[l1], (int32_t)qa.n),
-                           s_stage, lane);
+    // First iteration: the own leaves (their first K objects straight into
+    // the list when there are enough of them).
+    int32_t own_b = max(qa.leaf_begin[l0], 0);
+    const int32_t own_e = min(qa.leaf_end[l1], (int32_t)qa.n);
+    if (own_e - own_b >= K) {
+        w.fill(qa.pts, own_b, kq);
+        own_b += K;
+    }
+    w.template sweep<true>(qa.pts, own_b, own_e, s_stage, lane);
 
     // Subsequent iterations: the two Morton-order sub-visits in turn.
     const int32_t total = min((int32_t)qa.ctr->n_nodes, qa.node_cap);
