@@ -419,8 +419,9 @@ MKNN_API int32_t mknn_default_leaf_capacity(int32_t k);
  * x, y      device, n fp32 coordinates each, object id = index (as
  *           mknn_load_positions with MKNN_DEVICE); read in place.
  * n         0 .. MKNN_NOALLOC_MAX_N.
- * k         1 .. MKNN_K_LIMIT; lists of up to 128 keys run one query per
- *           lane, larger ones one query per wavefront (as mknn_query).
+ * k         1 .. MKNN_K_LIMIT; lists of up to 32 keys run one query per
+ *           lane, larger ones a group of lanes per query (the flavours
+ *           mknn_query's AUTO schedule picks).
  * leaf_capacity  0 = mknn_default_leaf_capacity(k); the maximum level is 16.
  * ids, d2   device, n * k entries each: row i (object i's query, object i
  *           excluded) is the dense row mknn_fetch returns for uniform k.

@@ -1299,7 +1299,8 @@ extern "C" int mknn_knn_noalloc(const float *x, const float *y, int64_t n, int32
     qa.out_cnt = counts;
     qa.build_epoch = epoch;
     qa.pos_mask = 0xffffffffu;
-    if (k > 128) launch_knn_wave(qa, k_class_wave(k), s);
+    // The flavour mknn_query's AUTO schedule picks.
+    if (k > kAutoLaneMaxK) launch_knn_group(qa, k_class_group(k), s);
     else launch_knn(qa, k_class(k), s);
     if (status) k_noalloc_status<<<1, 1, 0, s>>>(ix.ctr, status);
     return hipGetLastError() == hipSuccess ? MKNN_OK : MKNN_E_DEVICE;

@@ -63,7 +63,7 @@ def assert_same(got, exp, what):
     assert np.array_equal(gc, ec), what + ": counts differ"
 
 
-@pytest.mark.parametrize("k,th", [(8, 0), (32, 16), (200, 64)])
+@pytest.mark.parametrize("k,th", [(8, 0), (32, 16), (64, 32), (200, 64)])
 def test_noalloc_equals_context_path_on_calls_in_a_row(k, th):
     cases = (("clustered", 60000, 81), ("uniform", 7000, 82), ("duplicates", 3000, 83))
     for kind, n, seed in cases:
