@@ -322,6 +322,31 @@ def test_many_ticks_in_one_context():
             assert_rows_equal(c.fetch(), oracle.knn(x, y, k=5, threads=16), "k=5 tick %d" % t)
 
 
+def test_subset_queries_across_ticks_sizes_and_refits():
+    """Issuer subsets on consecutive ticks of one context: every build
+    needs the objects' sorted positions again, object counts change between
+    builds, and a refit tick keeps the last build's order."""
+    rng = np.random.default_rng(31)
+    with binding.Context(30_000, 5_000, 16, leaf_capacity=24) as c:
+        for t, (n, refit) in enumerate(((30_000, False), (30_000, False), (20_000, False),
+                                         (20_000, True), (30_000, False))):
+            if refit:  # the last build's objects, moved a little
+                x = np.clip(x + rng.uniform(-1e-4, 1e-4, n), 0, 0.999).astype(np.float32)
+            else:
+                x, y = family("clustered", n, 40 + t)
+            iss = rng.choice(n, 4000, replace=False).astype(np.int32)
+            ks = rng.integers(1, 17, len(iss)).astype(np.int32)
+            c.load_positions(x, y)
+            if refit:
+                c.refit_tick()
+            else:
+                c.advance_tick()
+            c.query(issuers=torch.from_numpy(iss).cuda(), ks=torch.from_numpy(ks).cuda())
+            say("subset tick %d n=%d refit=%s" % (t, n, refit))
+            assert_rows_equal(c.fetch(), oracle.knn(x, y, issuers=iss, ks=ks, threads=16),
+                              "subset tick %d" % t)
+
+
 # ---------------------------------------------------------------------------
 # Boundary behaviour
 # ---------------------------------------------------------------------------
