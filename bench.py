@@ -66,11 +66,11 @@ CPU_SAMPLE_SECONDS = 10.0
 # taken on (digest of the query kernel's sources without comments);
 # otherwise the roofline's traffic is null.
 MEASURED_TRAFFIC = [
-    {"digest": "b9114375deae7884", "workload": "clustered_1m", "leaf_capacity": 48, "max_level": 14,
+    {"digest": "44d04ec99edb738d", "workload": "clustered_1m", "leaf_capacity": 48, "max_level": 14,
      "fetch_bytes": 44963607, "write_bytes": 290682448, "valu_insts": 151083674},
-    {"digest": "b9114375deae7884", "workload": "clustered_1m", "leaf_capacity": 48, "max_level": 12,
+    {"digest": "44d04ec99edb738d", "workload": "clustered_1m", "leaf_capacity": 48, "max_level": 12,
      "fetch_bytes": 44579641, "write_bytes": 290688648, "valu_insts": 152106892},
-    {"digest": "b9114375deae7884", "workload": "clustered_1m", "leaf_capacity": 64, "max_level": 12,
+    {"digest": "44d04ec99edb738d", "workload": "clustered_1m", "leaf_capacity": 64, "max_level": 12,
      "fetch_bytes": 40062693, "write_bytes": 290701432, "valu_insts": 162653896},
 ]
 
@@ -84,14 +84,23 @@ def code_only(text):
     return " ".join(text.split())
 
 
-DIGEST_FILES = ("query.hip", "query_wave.hip", "query_group.hip", "query.hpp", "query_device.hpp",
-                "mknn_internal.hpp")
+# Sources a query kernel is compiled from: its flavour's file and the
+# shared headers.
+DIGEST_COMMON = ("query.hpp", "query_device.hpp", "mknn_internal.hpp")
+DIGEST_FLAVOUR = {"lane": "query.hip", "group": "query_group.hip", "wave": "query_wave.hip"}
 
 
-def query_source_digest(read=None):
+def digest_files(sweep="lane"):
+    return (DIGEST_FLAVOUR[sweep],) + DIGEST_COMMON
+
+
+DIGEST_FILES = digest_files("lane")
+
+
+def query_source_digest(read=None, sweep="lane"):
     import hashlib
     h = hashlib.sha256()
-    for f in DIGEST_FILES:
+    for f in digest_files(sweep):
         if read is None:
             with open(os.path.join(ROOT, "paper_1412_6170_amd", "csrc", f)) as fh:
                 text = fh.read()
@@ -106,7 +115,7 @@ def _measured(workload, leaf_capacity, max_level, sweep="lane"):
     for m in MEASURED_TRAFFIC:
         if (m["workload"] == workload and m["leaf_capacity"] == leaf_capacity
                 and m.get("max_level", 16) == max_level and m.get("sweep", "lane") == sweep):
-            digest = digest or query_source_digest()
+            digest = digest or query_source_digest(sweep=sweep)
             if m["digest"] == digest:
                 return m
     return None

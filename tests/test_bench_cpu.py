@@ -82,6 +82,21 @@ def test_digest_ignores_comments_not_code():
     assert bench.query_source_digest(changed.get) != base
 
 
+def test_digest_covers_only_the_flavours_sources():
+    files = set(bench.DIGEST_COMMON) | set(bench.DIGEST_FLAVOUR.values())
+    here = {f: open(os.path.join(ROOT, "paper_1412_6170_amd", "csrc", f)).read() for f in files}
+    lane, group = (bench.query_source_digest(here.get, sweep=s) for s in ("lane", "group"))
+    assert lane != group
+    edited = dict(here)
+    edited["query_group.hip"] = here["query_group.hip"] + "\nint extra_symbol;\n"
+    assert bench.query_source_digest(edited.get, sweep="lane") == lane
+    assert bench.query_source_digest(edited.get, sweep="group") != group
+    edited = dict(here)
+    edited["query_device.hpp"] = here["query_device.hpp"] + "\nint extra_symbol;\n"
+    assert bench.query_source_digest(edited.get, sweep="lane") != lane
+    assert bench.query_source_digest(edited.get, sweep="group") != group
+
+
 def test_valu_issue_fraction(monkeypatch):
     monkeypatch.setattr(bench, "MEASURED_TRAFFIC", _entries(bench.query_source_digest()))
     ms = 0.5
