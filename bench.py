@@ -57,6 +57,10 @@ TUNED_SCHEDULE = {
     "mixed_16m": {"leaf_capacity": 64, "max_level": 16, "sweep": "group", "group_k": False},
 }
 CPU_SAMPLE_SECONDS = 10.0
+# Maximum quadtree level of the served scenes: three radix passes per build
+# (the default level 16 takes four); a level-12 cell holds few objects even
+# in the cores of the 2M-object scenes at leaf capacity 32.
+SERVING_MAX_LEVEL = 12
 
 # HBM bytes per launch of the query kernel on clustered_1m for the schedules
 # the autotuner picks there, from two rocprofv3 --pmc runs per schedule
@@ -304,7 +308,8 @@ def run_serving(args):
         for t in range(args.scene_ticks):
             x, y, _, _, _ = w.tick(t)
             pos.append((torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()))
-        scenes.append(serving.Scene(sid, pos, k, leaf_capacity=args.leaf_capacity or 32))
+        scenes.append(serving.Scene(sid, pos, k, leaf_capacity=args.leaf_capacity or 32,
+                                    max_level=args.max_level or SERVING_MAX_LEVEL))
     torch.cuda.synchronize()
     budget = int(args.hbm_budget_gib * 2 ** 30)
     srv = serving.Server(scenes, hbm_budget=budget, slots=args.slots)

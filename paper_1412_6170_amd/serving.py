@@ -24,20 +24,23 @@ from . import binding
 
 
 class Scene:
-    def __init__(self, sid, positions, k, leaf_capacity=0):
+    def __init__(self, sid, positions, k, leaf_capacity=0, max_level=0):
         """positions: list of (x, y) device tensors, one per tick; they
-        stay unchanged while the scene is served."""
+        stay unchanged while the scene is served.  leaf_capacity and
+        max_level tune the scene's index (0: the library's defaults);
+        results never depend on them."""
         self.sid = sid
         self.positions = positions
         self.n = int(positions[0][0].numel())
         self.k = int(k)
         self.leaf_capacity = int(leaf_capacity)
+        self.max_level = int(max_level)
         self.ctx = None
         self.stream = None
         self.busy = False
         self.last_used = 0.0
         self.footprint = binding.footprint(n_max=self.n, k_max=self.k,
-                                           leaf_capacity=leaf_capacity)
+                                           leaf_capacity=leaf_capacity, max_level=max_level)
 
 
 class Request:
@@ -84,7 +87,7 @@ class Server:
         scene.stream = self.torch.cuda.Stream()   # default priority
         scene.ctx = binding.Context(scene.n, scene.n, scene.k,
                                     leaf_capacity=scene.leaf_capacity,
-                                    stream=scene.stream)
+                                    max_level=scene.max_level, stream=scene.stream)
         self.resident += scene.footprint
         self.admissions += 1
         return True
