@@ -309,7 +309,8 @@ def run_serving(args):
             x, y, _, _, _ = w.tick(t)
             pos.append((torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()))
         scenes.append(serving.Scene(sid, pos, k, leaf_capacity=args.leaf_capacity or 32,
-                                    max_level=args.max_level or SERVING_MAX_LEVEL))
+                                    max_level=args.max_level or SERVING_MAX_LEVEL,
+                                    tile_queries=args.tile_queries))
     torch.cuda.synchronize()
     budget = int(args.hbm_budget_gib * 2 ** 30)
     srv = serving.Server(scenes, hbm_budget=budget, slots=args.slots)
@@ -479,6 +480,8 @@ def main():
     ap.add_argument("--slots", type=int, default=4, help="ticks in flight at most")
     ap.add_argument("--hbm-budget-gib", type=float, default=64.0)
     ap.add_argument("--serving-seed", type=int, default=7)
+    ap.add_argument("--tile-queries", type=int, default=0, choices=(0, 8, 16, 32, 64),
+                    help="lane flavour queries per wavefront (0: automatic)")
     ap.add_argument("--no-serving", dest="serving_leg", action="store_false", default=True,
                     help="skip the serving leg of the default line")
     args = ap.parse_args()
@@ -559,6 +562,8 @@ def main():
     ctx = binding.Context(n, nq_max, k, leaf_capacity=th0 if th0 < 10 ** 9 else 0, k_hint=k,
                           max_level=l0, stream=stream.cuda_stream, timing=True,
                           counters=args.counters)
+    if args.tile_queries:
+        sched["tile_queries"] = args.tile_queries
     ctx.set_schedule(**{d: v for d, v in sched.items() if not (d == "leaf_capacity" and not v)})
 
     def step(s):

@@ -344,15 +344,22 @@ MKNN_API int mknn_set_leaf_capacity(mknn_ctx *ctx, int32_t th);
  * them).  leaf_capacity is th (Sec. 4.1); max_level is l_max (Sec. 4.1,
  * 1..16); sweep is an MKNN_SWEEP_* flavour (LANE applies to k <= 128;
  * larger k then use WAVE); group_k != 0 behaves as MKNN_FLAG_GROUP_K
- * (variable-k queries answered per k class, lane or group flavour).  The
- * index settings take effect at the next mknn_advance_tick, the sweep
- * settings at the next query.
+ * (variable-k queries answered per k class, lane or group flavour).
+ * tile_queries is the number of queries a wavefront of the lane flavour
+ * answers together (Sec. 4.2.1's grouping of nearby queries into one task):
+ * 64, 32, 16 or 8, or 0 for automatic (64, halved down to 8 while the
+ * launch still fits the GPU's resident wavefronts in one round: a launch
+ * too small to fill the GPU then finishes sooner, since fewer queries per
+ * wavefront share a smaller candidate set).  The index settings take
+ * effect at the next mknn_advance_tick, the sweep settings at the next
+ * query.
  */
 typedef struct mknn_schedule {
     int32_t leaf_capacity;
     int32_t max_level;
     int32_t sweep;
     int32_t group_k;
+    int32_t tile_queries;
 } mknn_schedule;
 
 /* mknn_get_schedule -- the settings in force.  Errors: MKNN_E_INVAL. */

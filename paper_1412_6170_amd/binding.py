@@ -55,7 +55,8 @@ class Stats(ctypes.Structure):
 
 class Schedule(ctypes.Structure):
     _fields_ = [("leaf_capacity", ctypes.c_int32), ("max_level", ctypes.c_int32),
-                ("sweep", ctypes.c_int32), ("group_k", ctypes.c_int32)]
+                ("sweep", ctypes.c_int32), ("group_k", ctypes.c_int32),
+                ("tile_queries", ctypes.c_int32)]
 
 
 class MknnError(RuntimeError):
@@ -482,14 +483,17 @@ class Context:
 
     def schedule(self):
         """The tuning settings in force: leaf_capacity, max_level, sweep
-        ("auto", "lane" or "wave") and group_k."""
+        ("auto", "lane", "wave" or "group"), group_k and tile_queries (lane
+        flavour queries per wavefront, 0 = automatic)."""
         sc = Schedule()
         self._check(lib().mknn_get_schedule(self._h, ctypes.byref(sc)))
         names = {v: k for k, v in SWEEPS.items()}
         return {"leaf_capacity": sc.leaf_capacity, "max_level": sc.max_level,
-                "sweep": names[sc.sweep], "group_k": bool(sc.group_k)}
+                "sweep": names[sc.sweep], "group_k": bool(sc.group_k),
+                "tile_queries": sc.tile_queries}
 
-    def set_schedule(self, leaf_capacity=None, max_level=None, sweep=None, group_k=None):
+    def set_schedule(self, leaf_capacity=None, max_level=None, sweep=None, group_k=None,
+                     tile_queries=None):
         """Change tuning settings (None: keep); results never depend on
         them."""
         cur = self.schedule()
@@ -498,6 +502,7 @@ class Context:
         sc.max_level = int(cur["max_level"] if max_level is None else max_level)
         sc.sweep = SWEEPS[cur["sweep"] if sweep is None else sweep]
         sc.group_k = int(cur["group_k"] if group_k is None else bool(group_k))
+        sc.tile_queries = int(cur["tile_queries"] if tile_queries is None else tile_queries)
         self._check(lib().mknn_set_schedule(self._h, ctypes.byref(sc)))
 
     def stats_ready(self):

@@ -21,6 +21,7 @@ struct mknn_ctx {
     int th = 0, L = 16, k_max = 1;
     int sweep = MKNN_SWEEP_AUTO;  // sweep flavour (mknn_schedule)
     bool group_k = false;         // variable k answered per k class
+    int tile_queries = 0;         // lane flavour queries per wavefront (0: automatic)
     hipStream_t stream = nullptr;
     bool own_stream = false;
     bool dead = false;         // sticky device error
@@ -595,6 +596,7 @@ QueryArgs base_query_args(mknn_ctx *c, int64_t nq, const int32_t *ks, int32_t k_
     qa.pos_mask = 0xffffffffu;
     qa.class_bounds = nullptr;
     qa.klass = 0;
+    qa.tile_queries = (uint32_t)c->tile_queries;
     return qa;
 }
 
@@ -1011,6 +1013,7 @@ int mknn_get_schedule(const mknn_ctx *c, mknn_schedule *out)
     out->max_level = c->L;
     out->sweep = c->sweep;
     out->group_k = c->group_k ? 1 : 0;
+    out->tile_queries = c->tile_queries;
     return MKNN_OK;
 }
 
@@ -1023,12 +1026,16 @@ int mknn_set_schedule(mknn_ctx *c, const mknn_schedule *sc)
     if (sc->sweep != MKNN_SWEEP_AUTO && sc->sweep != MKNN_SWEEP_LANE &&
         sc->sweep != MKNN_SWEEP_WAVE && sc->sweep != MKNN_SWEEP_GROUP)
         return fail(c, MKNN_E_INVAL, "unknown sweep flavour%s");
+    if (sc->tile_queries != 0 && sc->tile_queries != 8 && sc->tile_queries != 16 &&
+        sc->tile_queries != 32 && sc->tile_queries != 64)
+        return fail(c, MKNN_E_INVAL, "tile_queries must be 0, 8, 16, 32 or 64%s");
     if (node_capacity(c->cfg.n_max, sc->leaf_capacity, sc->max_level) > c->ix.node_cap)
         return fail(c, MKNN_E_CAPACITY, "schedule needs larger node tables than allocated%s");
     c->th = sc->leaf_capacity;
     c->L = sc->max_level;
     c->sweep = sc->sweep;
     c->group_k = sc->group_k != 0;
+    c->tile_queries = sc->tile_queries;
     return MKNN_OK;
 }
 

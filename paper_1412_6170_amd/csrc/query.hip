@@ -333,7 +333,7 @@ struct Lane {
     // A node is needed if its box may hold a key below some lane's
     // threshold (queued keys are not yet counted, so this errs on the side
     // of visiting).  A lane without a query has a zero threshold and the
-    // centre of the launch's last query, which is in the same wavefront: it
+    // centre of its tile's last query, which is in the same wavefront: it
     // wants a node only if that box contains the centre, and then so does
     // the lane of that query, so it adds no visit and needs no test of its
     // own.
@@ -393,13 +393,17 @@ __global__ __launch_bounds__(kWave) void k_knn_tiles(QueryArgs qa)
         q_begin = qa.class_bounds[qa.klass];
         q_count = qa.class_bounds[qa.klass + 1] - q_begin;
     }
-    const uint32_t tiles = (q_count + kWave - 1) / kWave;
+    // Tiles of qt consecutive queries, one per wavefront; lanes from qt on
+    // take the tile's last query, like the lanes past the last query.
+    const uint32_t qt = qa.tile_queries;
+    const uint32_t tiles = (q_count + qt - 1) / qt;
     const uint32_t tile = xcd_tile(blockIdx.x, tiles);
     if (tile >= tiles) return;  // whole wavefront idle
-    const uint32_t t = tile * kWave + lane;
+    const uint32_t t = tile * qt + lane;
+    const uint32_t tile_last = min(tile * qt + qt, q_count) - 1;
 
     Lane<K, P, FREE> ln;
-    ln.active = t < q_count;
+    ln.active = (uint32_t)lane < qt && t < q_count;
     // After refit ticks the objects have moved by up to D per axis since the
     // quadrant boxes were made; grow the boxes by D plus a margin that covers
     // the rounding of D and of the grown edges (2^-23 > 2 * 2^-25, the
@@ -413,7 +417,7 @@ __global__ __launch_bounds__(kWave) void k_knn_tiles(QueryArgs qa)
         // node is a wavefront-uniform branch.
         ln.pad = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(ln.pad)));
     }
-    const uint32_t tq = q_begin + (ln.active ? t : q_count - 1);
+    const uint32_t tq = q_begin + (ln.active ? t : tile_last);
     // Query centre, excluded object and sorted position to start from: an
     // object's own position and id, or a free centre's insertion position.
     int32_t qp, row;
@@ -640,10 +644,30 @@ int k_class(int k)
     return 128;
 }
 
-void launch_knn(const QueryArgs &qa, int kclass, hipStream_t s)
+// Queries per wavefront of a lane-flavour launch.  Automatic: 64, halved
+// (down to 8) while the halved tiles still fit the wavefronts the GPU holds
+// at once for this list size (256 CUs x 4 SIMDs x the wavefronts per SIMD
+// the kernel's registers allow), i.e. while the launch stays a single
+// round: its time is then that of its longest wavefront, which shrinks with
+// the tile's candidate set.  A per-class launch (query count known only on
+// the device) keeps 64.
+static uint32_t tile_queries_for(const QueryArgs &qa, int kclass)
 {
-    if (qa.nq == 0) return;
-    const uint32_t tiles = (qa.nq + kWave - 1) / kWave;
+    if (qa.tile_queries) return qa.tile_queries;
+    if (qa.class_bounds) return kWave;
+    const uint32_t per_simd = kclass <= 32 ? 4u : kclass == 64 ? 2u : 1u;
+    const uint64_t slots = 256ull * 4ull * per_simd;
+    uint32_t qt = kWave;
+    while (qt > 8 && ((uint64_t)qa.nq + qt / 2 - 1) / (qt / 2) <= slots) qt /= 2;
+    return qt;
+}
+
+void launch_knn(const QueryArgs &qa_in, int kclass, hipStream_t s)
+{
+    if (qa_in.nq == 0) return;
+    QueryArgs qa = qa_in;
+    qa.tile_queries = tile_queries_for(qa_in, kclass);
+    const uint32_t tiles = (qa.nq + qa.tile_queries - 1) / qa.tile_queries;
     const uint32_t groups = (tiles + kXcds - 1) / kXcds * kXcds;
     const dim3 grid(groups), block(kWave);
     if (qa.qpts) {

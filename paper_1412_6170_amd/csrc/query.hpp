@@ -44,6 +44,8 @@ struct QueryArgs {
     uint32_t build_epoch;        // epoch of the current index (refit drift tag)
     unsigned long long *counters;  // null, or [candidate steps, merges,
                                    // node visits, leaf sweeps, wavefronts]
+    uint32_t tile_queries;       // lane flavour: queries per wavefront (8..64;
+                                 // 0 = chosen at launch)
 };
 
 constexpr int kQueryClasses = 5;  // selection lists of 8, 16, 32, 64, 128 keys

@@ -24,17 +24,18 @@ from . import binding
 
 
 class Scene:
-    def __init__(self, sid, positions, k, leaf_capacity=0, max_level=0):
+    def __init__(self, sid, positions, k, leaf_capacity=0, max_level=0, tile_queries=0):
         """positions: list of (x, y) device tensors, one per tick; they
-        stay unchanged while the scene is served.  leaf_capacity and
-        max_level tune the scene's index (0: the library's defaults);
-        results never depend on them."""
+        stay unchanged while the scene is served.  leaf_capacity, max_level
+        and tile_queries tune the scene's index and query (0: the library's
+        defaults); results never depend on them."""
         self.sid = sid
         self.positions = positions
         self.n = int(positions[0][0].numel())
         self.k = int(k)
         self.leaf_capacity = int(leaf_capacity)
         self.max_level = int(max_level)
+        self.tile_queries = int(tile_queries)
         self.ctx = None
         self.stream = None
         self.busy = False
@@ -88,6 +89,8 @@ class Server:
         scene.ctx = binding.Context(scene.n, scene.n, scene.k,
                                     leaf_capacity=scene.leaf_capacity,
                                     max_level=scene.max_level, stream=scene.stream)
+        if scene.tile_queries:
+            scene.ctx.set_schedule(tile_queries=scene.tile_queries)
         self.resident += scene.footprint
         self.admissions += 1
         return True

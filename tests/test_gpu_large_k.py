@@ -155,7 +155,7 @@ def test_schedule_switches_between_ticks():
     exp = oracle.brute_knn(x, y, k=k, threads=16)
     with binding.Context(len(x), len(x), 256, leaf_capacity=16, max_level=16) as c:
         assert c.schedule() == {"leaf_capacity": 16, "max_level": 16, "sweep": "auto",
-                                "group_k": False}
+                                "group_k": False, "tile_queries": 0}
         for th, L, sweep in ((16, 16, "auto"), (64, 12, "wave"), (200, 8, "lane"),
                              (32, 16, "wave"), (16, 13, "lane")):
             c.set_schedule(leaf_capacity=th, max_level=L, sweep=sweep)
@@ -169,7 +169,8 @@ def test_schedule_switches_between_ticks():
         c.query(k=200)
         assert_rows_equal(c.fetch(), oracle.brute_knn(x, y, k=200, threads=16), "k=200")
         before = c.schedule()
-        for bad in ({"leaf_capacity": 0}, {"max_level": 17}, {"max_level": 0}):
+        for bad in ({"leaf_capacity": 0}, {"max_level": 17}, {"max_level": 0},
+                    {"tile_queries": 12}, {"tile_queries": 128}):
             with pytest.raises(binding.MknnError) as e:
                 c.set_schedule(**bad)
             assert e.value.code == -1

@@ -105,11 +105,13 @@ def test_query_time_without_waiting():
 
 
 def test_work_counters_and_node_count():
-    """MKNN_FLAG_COUNTERS: per query, one count per wavefront of 64 queries,
-    at least one leaf swept and one candidate per wavefront, totals that
-    restart with reset_timing, and results bit-equal to a context without
-    counters.  The node count equals the number of distinct quadrants on
-    the paths from the root to every leaf of the oracle's index."""
+    """MKNN_FLAG_COUNTERS: per query, one count per wavefront (64 queries
+    each with 64-query tiles; 8 each with the automatic tiles of a launch
+    this small), at least one leaf swept and one candidate per wavefront,
+    totals that restart with reset_timing, and results bit-equal to a
+    context without counters.  The node count equals the number of distinct
+    quadrants on the paths from the root to every leaf of the oracle's
+    index."""
     from tests.helpers import family
     import oracle
     x, y = family("clustered", 30000, 48)
@@ -121,6 +123,7 @@ def test_work_counters_and_node_count():
             quads.add((l, pre >> (2 * (lev - l))))
     with binding.Context(n, n, k, leaf_capacity=th, max_level=L, counters=True) as c, \
             binding.Context(n, n, k, leaf_capacity=th, max_level=L) as p:
+        c.set_schedule(tile_queries=64)
         rows = []
         for ctx in (c, p):
             run(ctx, x, y, k)
@@ -140,3 +143,12 @@ def test_work_counters_and_node_count():
         c.query(k=k, issuers=torch.from_numpy(issuers).cuda())
         c.sync()
         assert c.stats()["wavefronts"] == -(-len(issuers) // 64)
+        # Automatic tiles: 30,000 queries fit the GPU's resident wavefronts
+        # in one round even at 8 queries per wavefront.
+        c.set_schedule(tile_queries=0)
+        c.reset_timing()
+        c.query(k=k)
+        assert_same = [np.asarray(a).view(np.uint8) for a in c.fetch()[:3]]
+        for u, v in zip(assert_same, rows[1][:3]):
+            assert np.array_equal(u, np.asarray(v).view(np.uint8))
+        assert c.stats()["wavefronts"] == -(-n // 8)
