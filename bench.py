@@ -70,12 +70,12 @@ SERVING_MAX_LEVEL = 12
 # taken on (digest of the query kernel's sources without comments);
 # otherwise the roofline's traffic is null.
 MEASURED_TRAFFIC = [
-    {"digest": "44d04ec99edb738d", "workload": "clustered_1m", "leaf_capacity": 48, "max_level": 14,
-     "fetch_bytes": 44963607, "write_bytes": 290682448, "valu_insts": 151083674},
-    {"digest": "44d04ec99edb738d", "workload": "clustered_1m", "leaf_capacity": 48, "max_level": 12,
-     "fetch_bytes": 44579641, "write_bytes": 290688648, "valu_insts": 152106892},
-    {"digest": "44d04ec99edb738d", "workload": "clustered_1m", "leaf_capacity": 64, "max_level": 12,
-     "fetch_bytes": 40062693, "write_bytes": 290701432, "valu_insts": 162653896},
+    {"digest": "29750f4e6116cb76", "workload": "clustered_1m", "leaf_capacity": 48, "max_level": 14,
+     "fetch_bytes": 45013299, "write_bytes": 290688768, "valu_insts": 151193084},
+    {"digest": "29750f4e6116cb76", "workload": "clustered_1m", "leaf_capacity": 48, "max_level": 12,
+     "fetch_bytes": 44506527, "write_bytes": 290690304, "valu_insts": 152216302},
+    {"digest": "29750f4e6116cb76", "workload": "clustered_1m", "leaf_capacity": 64, "max_level": 12,
+     "fetch_bytes": 40044551, "write_bytes": 290697488, "valu_insts": 162763306},
 ]
 
 
