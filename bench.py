@@ -47,11 +47,11 @@ TH_CANDIDATES = (16, 24, 32, 48, 64, 96, 128, 192)
 # so 12 saves a radix pass over 16), sweep flavour (one query per lane, or
 # one query per wavefront: Sec. 4.2.1's cached and coalesced-writes
 # variants) and, for variable k, k grouping.
-SCHEDULE_SPACE = {"leaf_capacity": TH_CANDIDATES, "max_level": (12, 14, 16),
+SCHEDULE_SPACE = {"leaf_capacity": TH_CANDIDATES, "max_level": (8, 10, 12, 14, 16),
                   "sweep": ("lane", "wave", "group"), "group_k": (False, True)}
 # The autotuner's choice on MI355X per workload, used with --no-autotune.
 TUNED_SCHEDULE = {
-    "uniform_10k": {"leaf_capacity": 32, "max_level": 16, "sweep": "lane", "group_k": False},
+    "uniform_10k": {"leaf_capacity": 32, "max_level": 8, "sweep": "lane", "group_k": False},
     "clustered_1m": {"leaf_capacity": 48, "max_level": 14, "sweep": "lane", "group_k": False},
     "network_4m": {"leaf_capacity": 96, "max_level": 12, "sweep": "group", "group_k": False},
     "mixed_16m": {"leaf_capacity": 64, "max_level": 16, "sweep": "group", "group_k": False},
@@ -543,6 +543,9 @@ def main():
     if k > 128 and sched["sweep"] == "lane":
         sched["sweep"] = "group"
     space = {dim: list(v) for dim, v in SCHEDULE_SPACE.items()}
+    # Levels whose cells would average more than 16 objects of uniformly
+    # spread data are not tried (their trials on large workloads are slow).
+    space["max_level"] = [lv for lv in space["max_level"] if 4 ** lv * 16 >= n]
     if args.th_candidates:
         space["leaf_capacity"] = [int(v) for v in args.th_candidates.split(",")]
     if k > 128:
