@@ -370,8 +370,8 @@ MKNN_API int mknn_get_schedule(const mknn_ctx *ctx, mknn_schedule *out);
  * sized at mknn_create; a leaf capacity below, or a maximum level above,
  * the configured ones may need more nodes: such a schedule returns
  * MKNN_E_CAPACITY unless the tables still fit.  Errors: MKNN_E_INVAL
- * (leaf_capacity < 1, max_level outside 1..16, unknown sweep),
- * MKNN_E_CAPACITY.  On error nothing changes.
+ * (leaf_capacity < 1, max_level outside 1..16, unknown sweep, tile_queries
+ * not 0, 8, 16, 32 or 64), MKNN_E_CAPACITY.  On error nothing changes.
  */
 MKNN_API int mknn_set_schedule(mknn_ctx *ctx, const mknn_schedule *s);
 
