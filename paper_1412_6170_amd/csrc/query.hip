@@ -105,6 +105,9 @@ __device__ __forceinline__ void bitonic_merge(uint64_t (&a)[N])
     }
 }
 
+// Largest list filled straight from the own leaves (Lane::fill).
+constexpr int kFillMaxK = 64;
+
 // Lane-private selection of the K best keys (d2 bits << 32 | id).
 //
 // a[] holds the current best, sorted, in registers.  A lane asking for
@@ -126,9 +129,6 @@ __device__ __forceinline__ void bitonic_merge(uint64_t (&a)[N])
 // the list: an issuer lies in its own leaf, so it is met only in the first
 // sweep, whose candidates are checked by id as they are offered; a free
 // centre may exclude any object, so then every merge masks it by id.
-// Largest list filled straight from the own leaves (fill below).
-constexpr int kFillMaxK = 64;
-
 template <int K, int P>
 struct Selector {
     static constexpr uint32_t kSlotBytes = kWave * sizeof(uint64_t);  // slot stride
