@@ -22,6 +22,7 @@ struct mknn_ctx {
     int sweep = MKNN_SWEEP_AUTO;  // sweep flavour (mknn_schedule)
     bool group_k = false;         // variable k answered per k class
     int tile_queries = 0;         // lane flavour queries per wavefront (0: automatic)
+    int compute_units = 256;      // of the context's device (automatic query tiles)
     hipStream_t stream = nullptr;
     bool own_stream = false;
     bool dead = false;         // sticky device error
@@ -442,6 +443,12 @@ int mknn_create(const mknn_config *cfg, mknn_ctx **out)
         return MKNN_E_DEVICE;
     }
     int rc = MKNN_OK;
+    {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, cfg->device) ==
+                hipSuccess && cus > 0)
+            c->compute_units = cus;
+    }
     if (cfg->stream) {
         c->stream = (hipStream_t)cfg->stream;
     } else {
@@ -597,6 +604,7 @@ QueryArgs base_query_args(mknn_ctx *c, int64_t nq, const int32_t *ks, int32_t k_
     qa.class_bounds = nullptr;
     qa.klass = 0;
     qa.tile_queries = (uint32_t)c->tile_queries;
+    qa.compute_units = (uint32_t)c->compute_units;
     return qa;
 }
 
@@ -1306,6 +1314,12 @@ extern "C" int mknn_knn_noalloc(const float *x, const float *y, int64_t n, int32
     qa.out_cnt = counts;
     qa.build_epoch = epoch;
     qa.pos_mask = 0xffffffffu;
+    {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+            qa.compute_units = (uint32_t)cus;
+    }
     // The flavour mknn_query's AUTO schedule picks.
     if (k > kAutoLaneMaxK) launch_knn_group(qa, k_class_group(k), s);
     else launch_knn(qa, k_class(k), s);

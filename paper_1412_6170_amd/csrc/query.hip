@@ -646,8 +646,8 @@ int k_class(int k)
 
 // Queries per wavefront of a lane-flavour launch.  Automatic: 64, halved
 // (down to 8) while the halved tiles still fit the wavefronts the GPU holds
-// at once for this list size (256 CUs x 4 SIMDs x the wavefronts per SIMD
-// the kernel's registers allow), i.e. while the launch stays a single
+// at once for this list size (compute units x 4 SIMDs x the wavefronts per
+// SIMD the kernel's registers allow), i.e. while the launch stays a single
 // round: its time is then that of its longest wavefront, which shrinks with
 // the tile's candidate set.  A per-class launch (query count known only on
 // the device) keeps 64.
@@ -656,7 +656,8 @@ static uint32_t tile_queries_for(const QueryArgs &qa, int kclass)
     if (qa.tile_queries) return qa.tile_queries;
     if (qa.class_bounds) return kWave;
     const uint32_t per_simd = kclass <= 32 ? 4u : kclass == 64 ? 2u : 1u;
-    const uint64_t slots = 256ull * 4ull * per_simd;
+    const uint64_t cus = qa.compute_units ? qa.compute_units : 256u;
+    const uint64_t slots = cus * 4ull * per_simd;
     uint32_t qt = kWave;
     while (qt > 8 && ((uint64_t)qa.nq + qt / 2 - 1) / (qt / 2) <= slots) qt /= 2;
     return qt;

@@ -46,6 +46,7 @@ struct QueryArgs {
                                    // node visits, leaf sweeps, wavefronts]
     uint32_t tile_queries;       // lane flavour: queries per wavefront (8..64;
                                  // 0 = chosen at launch)
+    uint32_t compute_units;      // of the device (0 = 256); sizes automatic tiles
 };
 
 constexpr int kQueryClasses = 5;  // selection lists of 8, 16, 32, 64, 128 keys
