@@ -120,3 +120,34 @@ def test_readme_c_example_compiles(tmp_path):
                         "-I", os.path.join(root, "include"), str(src)],
                        capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
+
+
+def test_binding_structures_match_the_header(tmp_path):
+    """The ctypes mirrors of mknn_config, mknn_stats and mknn_schedule have
+    the header's field names, offsets and sizes (a C program compiled
+    against include/mknn.h prints them)."""
+    import subprocess
+    header = open(os.path.join(ROOT, "include", "mknn.h")).read()
+    pairs = (("mknn_config", binding.Config), ("mknn_stats", binding.Stats),
+             ("mknn_schedule", binding.Schedule))
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "mknn.h"', "int main(void) {"]
+    for cname, cls in pairs:
+        body = re.search(r"typedef struct %s \{(.*?)\} %s;" % (cname, cname), header, re.S).group(1)
+        body = re.sub(r"/\*.*?\*/", " ", body, flags=re.S)
+        names = re.findall(r"(\w+)\s*(?:\[\s*\d+\s*\])?\s*;", body)
+        assert names == [f for f, _ in cls._fields_], cname
+        lines.append('printf("%s %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f in names:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, f))
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)],
+                   check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                 check=True).stdout.splitlines())
+    for cname, cls in pairs:
+        assert int(got[cname]) == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert int(got["%s.%s" % (cname, f)]) == getattr(cls, f).offset, (cname, f)
