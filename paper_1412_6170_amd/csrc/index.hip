@@ -908,74 +908,76 @@ __device__ __forceinline__ uint32_t gallop_down(const uint32_t *__restrict__ lc,
     return lo;
 }
 
-// The level-l node leaf j contributes to either table (if any): leaf j
-// emits its forward nodes (its ancestors below the deepest quadrant shared
-// with leaf j-1, then itself) and its backward nodes (likewise with leaf
-// j+1).  One lane per (leaf, level), so the searches of different levels
-// of one leaf run side by side instead of one after another.
-__device__ __forceinline__ void emit_leaf_level(
+// Leaf levels run from min(cl, cr) + 1 >= 0 to lev <= 16 (17 at most, and
+// one to three for most leaves); a group of kLevelLanes lanes shares them
+// round robin, so the searches of different levels of one leaf run side by
+// side while a wavefront still serves several leaves.
+constexpr int kLevelLanes = 8;
+constexpr uint32_t kNodeEmitBlocks = 2048;  // of 256 threads: every SIMD filled
+
+// The nodes leaf j contributes to either table: its forward nodes (its
+// ancestors below the deepest quadrant shared with leaf j-1, then itself)
+// and its backward nodes (likewise with leaf j+1).  Lane r of the leaf's
+// group emits levels min(cl, cr) + 1 + r, + kLevelLanes, ...
+__device__ __forceinline__ void emit_leaf_levels(
     const uint32_t *__restrict__ codes, uint32_t n, const int32_t *__restrict__ leaf_begin,
     const int32_t *__restrict__ leaf_end, const int32_t *__restrict__ leaf_level,
     const uint32_t *__restrict__ leaf_code, const uint32_t *__restrict__ off_f,
     const uint32_t *__restrict__ off_r, uint32_t nl, uint32_t total, Node *__restrict__ fwd,
     Node *__restrict__ rev, int32_t *__restrict__ leaf_node_f, int32_t *__restrict__ leaf_node_r,
-    uint32_t node_cap, uint32_t j, int l)
+    uint32_t node_cap, uint32_t j, int r)
 {
     const int32_t b = leaf_begin[j], e = leaf_end[j];
     const int lev = leaf_level[j];
     const uint32_t code = leaf_code[j];
     const int cl = b > 0 ? common_level(codes[b - 1], code) : -1;
     const int cr = (uint32_t)e < n ? common_level(codes[e - 1], codes[e]) : -1;
-    if (l <= min(cl, cr) || l > lev) return;
-    const bool do_f = l > cl, do_r = l > cr;
     const uint32_t fbase = off_f[j];
     // Backward table: nodes of all later leaves come first.
     const uint32_t rbase = total - off_r[j] - (uint32_t)(lev - cr);
-    Node nd;
-    node_box(code, l, nd);
-    if (l == lev) {
-        nd.begin = b;
-        nd.end = e;
-        nd.leaf = (int32_t)j;
-        const uint32_t fi = fbase + (uint32_t)(l - cl - 1);
-        const uint32_t ri = rbase + (uint32_t)(l - cr - 1);
-        nd.skip = (int32_t)fi + 1;
-        if (fi < node_cap) fwd[fi] = nd;
-        leaf_node_f[j] = (int32_t)fi;
-        nd.skip = (int32_t)ri + 1;
-        if (ri < node_cap) rev[ri] = nd;
-        leaf_node_r[j] = (int32_t)ri;
-        return;
-    }
-    nd.leaf = -1;
-    if (do_f) {
-        const uint32_t hi = gallop_up(leaf_code, j, nl, code, l);
-        const uint32_t fi = fbase + (uint32_t)(l - cl - 1);
-        nd.begin = b;
-        nd.end = hi < nl ? leaf_begin[hi] : (int32_t)n;
-        nd.skip = hi < nl ? (int32_t)off_f[hi] : (int32_t)total;
-        if (fi < node_cap) fwd[fi] = nd;
-    }
-    if (do_r) {
-        const uint32_t lo = gallop_down(leaf_code, j, code, l);
-        const uint32_t ri = rbase + (uint32_t)(l - cr - 1);
-        nd.begin = leaf_begin[lo];
-        nd.end = e;
-        if (lo > 0) {
-            const int32_t pe = leaf_end[lo - 1];
-            const int pcr = common_level(codes[pe - 1], codes[pe]);
-            nd.skip = (int32_t)(total - off_r[lo - 1] - (uint32_t)(leaf_level[lo - 1] - pcr));
-        } else {
-            nd.skip = (int32_t)total;
+    for (int l = min(cl, cr) + 1 + r; l <= lev; l += kLevelLanes) {
+        const bool do_f = l > cl, do_r = l > cr;
+        Node nd;
+        node_box(code, l, nd);
+        if (l == lev) {
+            nd.begin = b;
+            nd.end = e;
+            nd.leaf = (int32_t)j;
+            const uint32_t fi = fbase + (uint32_t)(l - cl - 1);
+            const uint32_t ri = rbase + (uint32_t)(l - cr - 1);
+            nd.skip = (int32_t)fi + 1;
+            if (fi < node_cap) fwd[fi] = nd;
+            leaf_node_f[j] = (int32_t)fi;
+            nd.skip = (int32_t)ri + 1;
+            if (ri < node_cap) rev[ri] = nd;
+            leaf_node_r[j] = (int32_t)ri;
+            break;  // lev is the last level
         }
-        if (ri < node_cap) rev[ri] = nd;
+        nd.leaf = -1;
+        if (do_f) {
+            const uint32_t hi = gallop_up(leaf_code, j, nl, code, l);
+            const uint32_t fi = fbase + (uint32_t)(l - cl - 1);
+            nd.begin = b;
+            nd.end = hi < nl ? leaf_begin[hi] : (int32_t)n;
+            nd.skip = hi < nl ? (int32_t)off_f[hi] : (int32_t)total;
+            if (fi < node_cap) fwd[fi] = nd;
+        }
+        if (do_r) {
+            const uint32_t lo = gallop_down(leaf_code, j, code, l);
+            const uint32_t ri = rbase + (uint32_t)(l - cr - 1);
+            nd.begin = leaf_begin[lo];
+            nd.end = e;
+            if (lo > 0) {
+                const int32_t pe = leaf_end[lo - 1];
+                const int pcr = common_level(codes[pe - 1], codes[pe]);
+                nd.skip = (int32_t)(total - off_r[lo - 1] - (uint32_t)(leaf_level[lo - 1] - pcr));
+            } else {
+                nd.skip = (int32_t)total;
+            }
+            if (ri < node_cap) rev[ri] = nd;
+        }
     }
 }
-
-// Levels 0..16: 17 lanes would be needed for max_level 16 with a level-0
-// leaf; a leaf's levels run from min(cl, cr) + 1 >= 0 to lev <= 16, so each
-// leaf takes a group of 32 lanes (two leaves per wavefront).
-constexpr int kLevelLanes = 32;
 
 __global__ void k_node_emit(const uint32_t *__restrict__ codes, uint32_t n,
                             const int32_t *__restrict__ leaf_begin,
@@ -996,12 +998,12 @@ __global__ void k_node_emit(const uint32_t *__restrict__ codes, uint32_t n,
         if (blockIdx.x == 0 && threadIdx.x == 0) atomicMax(&ctr->bad_nodes, epoch);
         return;
     }
-    const int l = (int)(threadIdx.x % kLevelLanes);
+    const int r = (int)(threadIdx.x % kLevelLanes);
     const uint32_t per_block = blockDim.x / kLevelLanes;
     for (uint32_t j = blockIdx.x * per_block + threadIdx.x / kLevelLanes; j < nl;
          j += gridDim.x * per_block)
-        emit_leaf_level(codes, n, leaf_begin, leaf_end, leaf_level, leaf_code, off_f, off_r, nl,
-                        total, fwd, rev, leaf_node_f, leaf_node_r, node_cap, j, l);
+        emit_leaf_levels(codes, n, leaf_begin, leaf_end, leaf_level, leaf_code, off_f, off_r, nl,
+                         total, fwd, rev, leaf_node_f, leaf_node_r, node_cap, j, r);
 }
 
 
@@ -1111,7 +1113,7 @@ void launch_build_index(IndexBuffers &b, const float *x, const float *y, int64_t
                                              b.scan[2], b.ctr, b.leaf_level, b.leaf_code, b.cnt_f,
                                              b.cnt_r, epoch);
     const uint32_t gn = (uint32_t)((n + T / kLevelLanes - 1) / (T / kLevelLanes));
-    k_node_emit<<<gn < 8192 ? gn : 8192, T, 0, s>>>(codes, nn, b.leaf_begin, b.leaf_end,
+    k_node_emit<<<gn < kNodeEmitBlocks ? gn : kNodeEmitBlocks, T, 0, s>>>(codes, nn, b.leaf_begin, b.leaf_end,
                                                    b.leaf_level, b.leaf_code,
                                 b.cnt_f, b.cnt_r, b.ctr, b.fwd, b.rev, b.leaf_node_f,
                                 b.leaf_node_r, (uint32_t)b.node_cap, epoch);
