@@ -217,9 +217,10 @@ MKNN_API int mknn_advance_tick(mknn_ctx *ctx);
  * rebuilt every tick): instead of a full build, keep the last full build's
  * object order, leaves and node tables, take every object's position from
  * the current snapshot and record the largest per-axis displacement D of
- * any object since that build.  Queries then prune with every node box
- * grown by D (plus a rounding margin), so results stay exact; they only
- * get slower as D grows, which is the caller's signal to run a full
+ * any object since that build.  Each leaf's node box becomes the bounding
+ * box of its objects' current positions; queries prune with the inner node
+ * boxes grown by D (plus a rounding margin), so results stay exact; they
+ * only get slower as D grows, which is the caller's signal to run a full
  * mknn_advance_tick again (e.g. when query time grows by a chosen factor
  * over the time after the last build).  The snapshot must hold as many
  * objects as at the last full build (ids are positions, so they are the

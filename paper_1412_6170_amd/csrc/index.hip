@@ -1014,8 +1014,10 @@ __global__ void k_node_emit(const uint32_t *__restrict__ codes, uint32_t n,
 // each record takes the object's new position, and the largest per-axis
 // displacement D of any object since the build is recorded.  Every object of
 // a node's range lay inside the node's quadrant at the build, so it now lies
-// inside the quadrant grown by D on every side; the query kernel prunes with
-// those grown boxes, so results stay exact.
+// inside the quadrant grown by D on every side; the query kernels prune inner
+// nodes with those grown boxes.  A leaf's box is recomputed instead, as the
+// bounding box of its objects' current positions (a leaf holds few objects,
+// and the distance computations happen at leaves), so results stay exact.
 // ---------------------------------------------------------------------------
 
 __global__ void k_refit(const float *__restrict__ x, const float *__restrict__ y, uint32_t n,
@@ -1053,6 +1055,56 @@ __global__ void k_refit(const float *__restrict__ x, const float *__restrict__ y
     }
 }
 
+// Leaf boxes of a refit tick: the box of each leaf's node, in both tables,
+// becomes the bounding box [min, max] of its objects' current positions.
+// Its edges are coordinates of the leaf's objects, and rounding is monotone,
+// so the unpadded lower bound (gap to the box, squared and summed in fp32)
+// never exceeds the computed d2 of any of them.  A group of kBoxLanes lanes
+// per leaf strides over its objects, then reduces across the group.
+constexpr int kBoxLanes = 8;
+constexpr uint32_t kBoxBlocks = 2048;
+
+__global__ __launch_bounds__(256) void k_refit_leaf_boxes(
+    const Point *__restrict__ pts, const int32_t *__restrict__ leaf_begin,
+    const int32_t *__restrict__ leaf_end, const int32_t *__restrict__ leaf_node_f,
+    const int32_t *__restrict__ leaf_node_r, const IndexCounters *__restrict__ ctr,
+    Node *__restrict__ fwd, Node *__restrict__ rev, uint32_t node_cap)
+{
+    const uint32_t nl = ctr->n_leaves;
+    const int r = (int)(threadIdx.x % kBoxLanes);
+    const uint32_t per_block = blockDim.x / kBoxLanes;
+    // Every lane of a wavefront runs the same iterations (the shuffles below
+    // need all of them); lanes past the last leaf reduce an empty box.
+    for (uint32_t j0 = blockIdx.x * per_block; j0 < nl; j0 += gridDim.x * per_block) {
+        const uint32_t j = j0 + threadIdx.x / kBoxLanes;
+        float x0 = __builtin_inff(), y0 = __builtin_inff();
+        float x1 = -__builtin_inff(), y1 = -__builtin_inff();
+        if (j < nl) {
+            const int32_t e = leaf_end[j];
+            for (int32_t i = leaf_begin[j] + r; i < e; i += kBoxLanes) {
+                const Point p = pts[i];
+                x0 = fminf(x0, p.x);
+                y0 = fminf(y0, p.y);
+                x1 = fmaxf(x1, p.x);
+                y1 = fmaxf(y1, p.y);
+            }
+        }
+#pragma unroll
+        for (int d = 1; d < kBoxLanes; d <<= 1) {
+            x0 = fminf(x0, __shfl_xor(x0, d, kWave));
+            y0 = fminf(y0, __shfl_xor(y0, d, kWave));
+            x1 = fmaxf(x1, __shfl_xor(x1, d, kWave));
+            y1 = fmaxf(y1, __shfl_xor(y1, d, kWave));
+        }
+        if (j < nl && r == 0) {
+            const float4 box = make_float4(x0, y0, x1, y1);
+            const uint32_t f = (uint32_t)leaf_node_f[j], b = (uint32_t)leaf_node_r[j];
+            if (f < node_cap) *reinterpret_cast<float4 *>(&fwd[f].x0) = box;
+            if (b < node_cap) *reinterpret_cast<float4 *>(&rev[b].x0) = box;
+        }
+    }
+}
+
 // The drift word starts at this refit's epoch with a zero displacement, by
 // a plain store ahead of k_refit's maxima.
 __global__ void k_drift_start(IndexCounters *ctr, uint32_t epoch)
@@ -1069,6 +1121,12 @@ void launch_refit(IndexBuffers &b, const float *x, const float *y, int64_t n, ui
     const int64_t g = (n + T - 1) / T;
     k_refit<<<(uint32_t)(g < 1024 ? g : 1024), T, 0, s>>>(x, y, (uint32_t)n, b.pts, b.anchor, b.ctr,
                                                          epoch);
+    // At most one leaf per object; the grid strides over the leaf count,
+    // which is only known on the device.
+    const int64_t gb = (n + T / kBoxLanes - 1) / (T / kBoxLanes);
+    k_refit_leaf_boxes<<<(uint32_t)(gb < kBoxBlocks ? gb : kBoxBlocks), T, 0, s>>>(
+        b.pts, b.leaf_begin, b.leaf_end, b.leaf_node_f, b.leaf_node_r, b.ctr, b.fwd, b.rev,
+        (uint32_t)b.node_cap);
 }
 
 int64_t node_capacity(int64_t n, int th, int L)

@@ -40,7 +40,8 @@ struct __align__(16) Point {
 // range of sorted objects under the node; skip is the index of the first
 // node after its subtree; leaf is the leaf index for leaves, -1 otherwise.
 struct __align__(16) Node {
-    float x0, y0, x1, y1;  // quadrant box [x0,x1) x [y0,y1), exact edges
+    float x0, y0, x1, y1;  // quadrant box [x0,x1) x [y0,y1), exact edges; after a refit
+                           // tick a leaf's is its objects' bounding box
     int32_t begin, end;
     int32_t skip;
     int32_t leaf;

@@ -337,9 +337,13 @@ struct Lane {
     // wants a node only if that box contains the centre, and then so does
     // the lane of that query, so it adds no visit and needs no test of its
     // own.
+    // After refit ticks inner boxes are grown by pad; leaf boxes already
+    // bound their objects' current positions and are taken as they are.
     __device__ __forceinline__ bool wants(const Node &nd) const
     {
-        return __float_as_uint(box_lower_bound(qx, qy, nd, pad)) <= (uint32_t)(sel.thr >> 32);
+        const float lb = nd.leaf >= 0 ? box_lower_bound_exact(qx, qy, nd)
+                                      : box_lower_bound(qx, qy, nd, pad);
+        return __float_as_uint(lb) <= (uint32_t)(sel.thr >> 32);
     }
     // The same with unpadded boxes (right after a full build): x - 0 = x, so
     // the bound is identical, with four fewer operations.
@@ -405,9 +409,10 @@ __global__ __launch_bounds__(kWave) void k_knn_tiles(QueryArgs qa)
     Lane<K, P, FREE> ln;
     ln.active = (uint32_t)lane < qt && t < q_count;
     // After refit ticks the objects have moved by up to D per axis since the
-    // quadrant boxes were made; grow the boxes by D plus a margin that covers
-    // the rounding of D and of the grown edges (2^-23 > 2 * 2^-25, the
-    // largest rounding error of a difference or a sum below 1).
+    // quadrant boxes were made; grow the inner nodes' boxes by D plus a
+    // margin that covers the rounding of D and of the grown edges (2^-23 >
+    // 2 * 2^-25, the largest rounding error of a difference or a sum below
+    // 1).  Leaf boxes are recomputed by the refit and not grown.
     ln.pad = 0.0f;
     {
         const unsigned long long dw = qa.ctr->drift;

@@ -228,8 +228,9 @@ struct GroupQuery {
     // add no visit (see the lane flavour) and are not tested apart.
     __device__ __forceinline__ bool wants(const Node &nd) const
     {
-        const float lb = pad == 0.0f ? box_lower_bound_exact(qx, qy, nd)
-                                     : box_lower_bound(qx, qy, nd, pad);
+        // Leaf boxes after a refit bound their objects as they are.
+        const float lb = (pad == 0.0f || nd.leaf >= 0) ? box_lower_bound_exact(qx, qy, nd)
+                                                       : box_lower_bound(qx, qy, nd, pad);
         return __float_as_uint(lb) <= (uint32_t)(thr >> 32);
     }
 

@@ -143,7 +143,9 @@ struct WaveQuery {
 
     __device__ __forceinline__ bool wants(const Node &nd) const
     {
-        const float lb = pad == 0.0f ? box_lower_bound_exact(qx, qy, nd) : box_lower_bound(qx, qy, nd, pad);
+        // Leaf boxes after a refit bound their objects as they are.
+        const float lb = (pad == 0.0f || nd.leaf >= 0) ? box_lower_bound_exact(qx, qy, nd)
+                                                       : box_lower_bound(qx, qy, nd, pad);
         return __float_as_uint(lb) <= (uint32_t)(sel.thr >> 32);
     }
 

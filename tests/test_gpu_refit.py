@@ -56,6 +56,37 @@ def test_refit_ticks_moving_clusters(L):
             check(got, oracle.knn(x, y, k=k, th=32, threads=16))
 
 
+@pytest.mark.parametrize("sweep,k", [("lane", 24), ("group", 64), ("wave", 40)])
+def test_refit_every_sweep_flavour(sweep, k):
+    """Refit ticks with each sweep flavour: leaf boxes are the bounding boxes
+    of the objects' current positions, inner boxes the build's quadrants
+    grown by the drift.  Objects drift over several ticks (leaves spread
+    past their quadrants); all queries, a subset and free centres each
+    match brute force."""
+    w = workloads.clustered_1m(n=20_000, ticks=5)
+    rng = np.random.default_rng(11)
+    with binding.Context(w.n, w.n, k, leaf_capacity=16, max_level=14) as c:
+        c.set_schedule(sweep=sweep)
+        for t in range(w.ticks):
+            x, y, _, _, _ = w.tick(t)
+            say("refit every flavour: %s k=%d tick %d" % (sweep, k, t))
+            c.load_positions(x, y)
+            if t == 0:
+                c.advance_tick()
+            else:
+                c.refit_tick()
+            c.query(k=k)
+            check(c.fetch(), oracle.brute_knn(x, y, k=k, threads=16))
+            iss = rng.integers(0, w.n, 1500).astype(np.int32)
+            c.query(issuers=iss, k=k)
+            check(c.fetch(), oracle.brute_knn(x, y, issuers=iss, k=k, threads=16))
+            qx = rng.random(1000, dtype=np.float32)
+            qy = rng.random(1000, dtype=np.float32)
+            c.query_points(qx, qy, k=k)
+            check(c.fetch(), oracle.brute_knn_points(x, y, qx, qy, k=k, threads=16))
+        assert c.stats()["refits"] == w.ticks - 1
+
+
 def test_refit_after_large_moves_and_all_query_kinds():
     x0, y0 = family("clustered", 20_000, 3)
     rng = np.random.default_rng(5)
