@@ -70,22 +70,22 @@ SERVING_MAX_LEVEL = 12
 # taken on (digest of the query kernel's sources without comments);
 # otherwise the roofline's traffic is null.
 MEASURED_TRAFFIC = [
-    {"digest": "82d07d3fab768840", "workload": "clustered_1m", "leaf_capacity": 32, "max_level": 12,
-     "fetch_bytes": 50818197, "write_bytes": 290671472, "valu_insts": 145872259},
-    {"digest": "82d07d3fab768840", "workload": "clustered_1m", "leaf_capacity": 48, "max_level": 12,
-     "fetch_bytes": 44602359, "write_bytes": 290687280, "valu_insts": 152216302},
-    {"digest": "82d07d3fab768840", "workload": "clustered_1m", "leaf_capacity": 64, "max_level": 12,
-     "fetch_bytes": 40044231, "write_bytes": 290696120, "valu_insts": 162763306},
-    {"digest": "82d07d3fab768840", "workload": "clustered_1m", "leaf_capacity": 96, "max_level": 12,
-     "fetch_bytes": 37431020, "write_bytes": 290741688, "valu_insts": 174469002},
-    {"digest": "82d07d3fab768840", "workload": "clustered_1m", "leaf_capacity": 32, "max_level": 14,
-     "fetch_bytes": 51414977, "write_bytes": 290701600, "valu_insts": 144770354},
-    {"digest": "82d07d3fab768840", "workload": "clustered_1m", "leaf_capacity": 48, "max_level": 14,
-     "fetch_bytes": 45062446, "write_bytes": 290714576, "valu_insts": 151193084},
-    {"digest": "82d07d3fab768840", "workload": "clustered_1m", "leaf_capacity": 64, "max_level": 14,
-     "fetch_bytes": 40341197, "write_bytes": 290695216, "valu_insts": 161846035},
-    {"digest": "82d07d3fab768840", "workload": "clustered_1m", "leaf_capacity": 96, "max_level": 14,
-     "fetch_bytes": 37596573, "write_bytes": 290731256, "valu_insts": 173701547},
+    {"digest": "9adfa7701465ad9e", "workload": "clustered_1m", "leaf_capacity": 32, "max_level": 12,
+     "fetch_bytes": 50939307, "write_bytes": 290666216, "valu_insts": 145872259},
+    {"digest": "9adfa7701465ad9e", "workload": "clustered_1m", "leaf_capacity": 48, "max_level": 12,
+     "fetch_bytes": 44609942, "write_bytes": 290686464, "valu_insts": 152216302},
+    {"digest": "9adfa7701465ad9e", "workload": "clustered_1m", "leaf_capacity": 64, "max_level": 12,
+     "fetch_bytes": 40127199, "write_bytes": 290706072, "valu_insts": 162763306},
+    {"digest": "9adfa7701465ad9e", "workload": "clustered_1m", "leaf_capacity": 96, "max_level": 12,
+     "fetch_bytes": 37453098, "write_bytes": 290729992, "valu_insts": 174469002},
+    {"digest": "9adfa7701465ad9e", "workload": "clustered_1m", "leaf_capacity": 32, "max_level": 14,
+     "fetch_bytes": 51718662, "write_bytes": 290709408, "valu_insts": 144770354},
+    {"digest": "9adfa7701465ad9e", "workload": "clustered_1m", "leaf_capacity": 48, "max_level": 14,
+     "fetch_bytes": 45067886, "write_bytes": 290707864, "valu_insts": 151193084},
+    {"digest": "9adfa7701465ad9e", "workload": "clustered_1m", "leaf_capacity": 64, "max_level": 14,
+     "fetch_bytes": 40372394, "write_bytes": 290692296, "valu_insts": 161846035},
+    {"digest": "9adfa7701465ad9e", "workload": "clustered_1m", "leaf_capacity": 96, "max_level": 14,
+     "fetch_bytes": 37656760, "write_bytes": 290724896, "valu_insts": 173701547},
 ]
 
 
