@@ -274,6 +274,42 @@ def test_variable_k_every_class(device_inputs, group_k):
     assert_rows_equal(got, oracle.knn(x, y, ks=ks, th=24, threads=16), "two classes")
 
 
+def test_subset_orders_radix_and_owner_table():
+    """Subset queries are ordered by a radix sort of their positions when
+    they are fewer than one per 64 objects, else through a table of the
+    issuers' positions (repeated issuers listed after the others).  Both
+    orders, either side of the switch, with and without repeats, many more
+    queries than objects, every object in shuffled order, and calls in a row
+    on one context (the table clears itself after each call), each row
+    against the oracle."""
+    n = 20_000
+    x, y = family("clustered", n, 27)
+    rng = np.random.default_rng(27)
+    # The switch: ceil(n / 64) = 313 <= nq + 1.
+    cases = [
+        ("radix, distinct", rng.choice(n, 311, replace=False)),
+        ("table, distinct", rng.choice(n, 312, replace=False)),
+        ("table, distinct, more", rng.choice(n, 700, replace=False)),
+        ("table, repeats", rng.integers(0, n, 8000)),
+        ("table, more queries than objects", rng.integers(0, n, 50_000)),
+        ("table, every object shuffled", rng.permutation(n)),
+        ("radix, repeats", np.array([7, 7, 19_999, 0, 7] * 40)),
+    ]
+    with binding.Context(n, 50_000, 24) as c:
+        c.load_positions(x, y)
+        c.advance_tick()
+        for rnd in range(2):
+            for what, iss in cases:
+                iss = np.asarray(iss, np.int32)
+                ks = rng.choice([1, 5, 12, 24], len(iss)).astype(np.int32)
+                say("subset order: %s (%d queries), call %d" % (what, len(iss), rnd))
+                c.query(k=12, issuers=iss)
+                assert_rows_equal(c.fetch(), oracle.knn(x, y, issuers=iss, k=12, threads=16), what)
+                c.query(issuers=iss, ks=ks)
+                assert_rows_equal(c.fetch(), oracle.knn(x, y, issuers=iss, ks=ks, threads=16),
+                                  what + ", variable k")
+
+
 def test_repeated_issuers_and_empty_query():
     x, y = family("uniform", 800, 26)
     iss = np.array([5, 5, 799, 0, 5], np.int32)
