@@ -41,7 +41,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TH_CANDIDATES = (16, 24, 32, 48, 64, 96, 128, 192)
+TH_CANDIDATES = (16, 24, 32, 48, 64, 96, 128, 192, 256, 384)
 # The autotuner's search space: leaf capacity, maximum quadtree level (l_max,
 # Sec. 4.1: the build sorts only the top 2 * l_max bits of the Morton codes,
 # so 12 saves a radix pass over 16), sweep flavour (one query per lane, or
@@ -53,8 +53,8 @@ SCHEDULE_SPACE = {"leaf_capacity": TH_CANDIDATES, "max_level": (8, 10, 12, 14, 1
 TUNED_SCHEDULE = {
     "uniform_10k": {"leaf_capacity": 24, "max_level": 8, "sweep": "lane", "group_k": False},
     "clustered_1m": {"leaf_capacity": 48, "max_level": 14, "sweep": "lane", "group_k": False},
-    "network_4m": {"leaf_capacity": 96, "max_level": 12, "sweep": "group", "group_k": False},
-    "mixed_16m": {"leaf_capacity": 64, "max_level": 16, "sweep": "group", "group_k": False},
+    "network_4m": {"leaf_capacity": 128, "max_level": 12, "sweep": "group", "group_k": False},
+    "mixed_16m": {"leaf_capacity": 384, "max_level": 16, "sweep": "group", "group_k": False},
 }
 CPU_SAMPLE_SECONDS = 10.0
 # Maximum quadtree level of the served scenes: three radix passes per build
