@@ -47,13 +47,13 @@ def rows_block(ctx, r0, r1, k):
 
 
 def test_network_4m_all_ticks():
-    """The road-graph workload in the benchmark's configuration (leaf
-    capacity 64, maximum level 12, 4M objects, a fresh half of them querying
+    """The road-graph workload in the benchmark's stored configuration (leaf
+    capacity 128, maximum level 12, 4M objects, a fresh half of them querying
     each tick with k in {8,16,32,64}): all 20 ticks on the GPU, the whole
     result against the oracle on ticks 0, 10 and 19, and 1,000 sampled
     queries per tick against brute force."""
     w = workloads.network_4m()
-    with binding.Context(w.n, w.n // 2 + 1, 64, leaf_capacity=64, k_hint=64, max_level=12) as c:
+    with binding.Context(w.n, w.n // 2 + 1, 64, leaf_capacity=128, k_hint=64, max_level=12) as c:
         for t in range(w.ticks):
             x, y, iss, ks, _ = w.tick(t)
             print("network_4m tick %d: %d queries" % (t, len(iss)), flush=True)
@@ -77,13 +77,13 @@ def test_network_4m_all_ticks():
 
 
 def test_mixed_16m_k128_ticks_0_50_99():
-    """The 16M-object, k = 128 workload in the benchmark's configuration
-    (leaf capacity 64), ticks 0, 50 and 99: 200 sampled queries per tick
+    """The 16M-object, k = 128 workload in the benchmark's stored
+    configuration (leaf capacity 384), ticks 0, 50 and 99: 200 sampled queries per tick
     against brute force, and every per-row invariant on a block of 65,536
     consecutive rows (all rows would be 16 GB of results)."""
     w = workloads.mixed_16m()
     k = 128
-    with binding.Context(w.n, w.n, k, leaf_capacity=64, k_hint=k) as c:
+    with binding.Context(w.n, w.n, k, leaf_capacity=384, k_hint=k) as c:
         for t in (0, 50, 99):
             x, y, _, _, _ = w.tick(t)
             print("mixed_16m tick %d" % t, flush=True)
