@@ -52,7 +52,7 @@ SCHEDULE_SPACE = {"leaf_capacity": TH_CANDIDATES, "max_level": (8, 10, 12, 14, 1
 # The autotuner's choice on MI355X per workload, used with --no-autotune.
 TUNED_SCHEDULE = {
     "uniform_10k": {"leaf_capacity": 24, "max_level": 8, "sweep": "lane", "group_k": False},
-    "clustered_1m": {"leaf_capacity": 48, "max_level": 14, "sweep": "lane", "group_k": False},
+    "clustered_1m": {"leaf_capacity": 32, "max_level": 12, "sweep": "lane", "group_k": False},
     "network_4m": {"leaf_capacity": 128, "max_level": 12, "sweep": "group", "group_k": False},
     "mixed_16m": {"leaf_capacity": 384, "max_level": 16, "sweep": "group", "group_k": False},
 }
