@@ -14,5 +14,5 @@ def pytest_configure(config):
 
 
 def pytest_collection_modifyitems(config, items):
-    # GPU tests run in one process on the GPU machine; nothing to reorder here.
+    # GPU tests run in one process, in file order; nothing to reorder here.
     return
