@@ -590,7 +590,8 @@ def main():
         if args.autotune and any(space.values()):
             best, times = binding.autotune_schedule(
                 ctx, step, space["leaf_capacity"], max_levels=space["max_level"],
-                sweeps=space["sweep"], group_k=space["group_k"], repeats=3, rounds=2)
+                sweeps=space["sweep"], group_k=space["group_k"], repeats=3, rounds=2,
+                finalists=4, final_repeats=8)
             tune = {"chosen": best, "device_ms_per_tick": times}
             print("bench: autotuned schedule %s" % (best,), file=sys.stderr, flush=True)
         sched = ctx.schedule()

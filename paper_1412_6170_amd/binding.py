@@ -624,11 +624,15 @@ def autotune_leaf_capacity(ctx, run_tick, candidates, repeats=3):
 
 
 def autotune_schedule(ctx, run_tick, leaf_capacities, max_levels=(), sweeps=(), group_k=(),
-                      repeats=3, rounds=2):
+                      repeats=3, rounds=2, finalists=1, final_repeats=8):
     """Pick the schedule with the shortest device time per tick, one
     dimension at a time (coordinate descent over leaf capacity, maximum
     level, sweep flavour and k grouping, `rounds` passes; an empty list
-    leaves that dimension as it is).
+    leaves that dimension as it is).  With finalists > 1, the fastest
+    `finalists` settings seen are timed again, in two interleaved passes of
+    `final_repeats` ticks each, and the lowest mean of those decides:
+    settings a few percent apart are otherwise told apart by the noise of
+    a few ticks.  Their entries in the returned times are those means.
 
     ctx must have been created with timing enabled and with node tables
     that fit every candidate (the smallest leaf capacity and the largest
@@ -640,21 +644,23 @@ def autotune_schedule(ctx, run_tick, leaf_capacities, max_levels=(), sweeps=(), 
     times = {}
     i = [0]
 
-    def measure(**kw):
-        key = tuple(sorted(kw.items()))
-        if key in times:
-            return times[key]
+    def timed(kw, reps):
         ctx.set_schedule(**kw)
         run_tick(i[0])
         i[0] += 1
         ctx.sync()
         ctx.reset_timing()
-        for _ in range(repeats):
+        for _ in range(reps):
             run_tick(i[0])
             i[0] += 1
         ctx.sync()
         st = ctx.stats()
-        times[key] = st["ms_build_mean"] + st["ms_query_mean"]
+        return st["ms_build_mean"] + st["ms_query_mean"]
+
+    def measure(**kw):
+        key = tuple(sorted(kw.items()))
+        if key not in times:
+            times[key] = timed(kw, repeats)
         return times[key]
 
     best = ctx.schedule()
@@ -669,6 +675,15 @@ def autotune_schedule(ctx, run_tick, leaf_capacities, max_levels=(), sweeps=(), 
                 cand = dict(best, **{name: v})
                 trial[v] = measure(**cand)
             best = dict(best, **{name: min(trial, key=trial.get)})
+    if finalists > 1 and len(times) > 1:
+        top = sorted(times, key=times.get)[:finalists]
+        acc = {key: [] for key in top}
+        for _ in range(2):
+            for key in top:
+                acc[key].append(timed(dict(key), final_repeats))
+        for key in top:
+            times[key] = sum(acc[key]) / len(acc[key])
+        best = dict(min(top, key=times.get))
     ctx.set_schedule(**best)
     ctx.sync()
     ctx.reset_timing()

@@ -3,7 +3,9 @@ It refits from the second tick on, keeps refitting while the query two
 ticks back stays within the factor of the query of the last full build,
 rebuilds when it does not, after max_refits refits in a row or when the
 object count changes, and never waits for the last query (which would
-leave the GPU idle)."""
+leave the GPU idle).  Also the autotuner's finalists stage."""
+import pytest
+
 from paper_1412_6170_amd import binding
 
 
@@ -76,3 +78,47 @@ def test_a_new_object_count_rebuilds():
     sizes = [10, 10, 10, 12, 12, 9, 9]
     kinds = [pol.tick(ctx, [0.5] * m, [0.5] * m) for m in sizes]
     assert kinds == ["build", "refit", "refit", "build", "refit", "build", "refit"]
+
+
+class _TunedCtx:
+    """A context whose timings are scripted per leaf capacity: the first
+    timing of a setting may be off (noise), later ones are its true cost."""
+
+    def __init__(self, first, true):
+        self.sched = {"leaf_capacity": 16, "max_level": 12, "sweep": "lane", "group_k": False,
+                      "tile_queries": 0}
+        self.first, self.true, self.seen = first, true, set()
+
+    def schedule(self):
+        return dict(self.sched)
+
+    def set_schedule(self, **kw):
+        self.sched.update(kw)
+
+    def sync(self):
+        pass
+
+    def reset_timing(self):
+        pass
+
+    def stats(self):
+        th = self.sched["leaf_capacity"]
+        ms = self.first.get(th, self.true[th]) if th not in self.seen else self.true[th]
+        self.seen.add(th)
+        return {"ms_build_mean": 0.0, "ms_query_mean": ms}
+
+
+def test_autotune_finalists_retime_the_fastest_settings():
+    """One noisy timing makes leaf capacity 48 look fastest; coordinate
+    descent alone keeps it, the finalists stage times the fastest settings
+    again and picks 32, the fastest on average."""
+    true = {16: 1.00, 32: 0.90, 48: 0.95}
+    first = {48: 0.80}
+    best, _ = binding.autotune_schedule(_TunedCtx(first, true), lambda i: None, (16, 32, 48))
+    assert best["leaf_capacity"] == 48
+    best, times = binding.autotune_schedule(_TunedCtx(first, true), lambda i: None, (16, 32, 48),
+                                            finalists=2, final_repeats=2)
+    assert best["leaf_capacity"] == 32
+    means = {dict(p.split("=") for p in key.split(", "))["leaf_capacity"]: v
+             for key, v in times.items()}
+    assert means["32"] == pytest.approx(0.90) and means["48"] == pytest.approx(0.95)
