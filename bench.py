@@ -70,6 +70,8 @@ SERVING_MAX_LEVEL = 12
 # taken on (digest of the query kernel's sources without comments);
 # otherwise the roofline's traffic is null.
 MEASURED_TRAFFIC = [
+    {"digest": "9adfa7701465ad9e", "workload": "clustered_1m", "leaf_capacity": 24, "max_level": 12,
+     "fetch_bytes": 55443392, "write_bytes": 290688408, "valu_insts": 144883969},
     {"digest": "9adfa7701465ad9e", "workload": "clustered_1m", "leaf_capacity": 32, "max_level": 12,
      "fetch_bytes": 50939307, "write_bytes": 290666216, "valu_insts": 145872259},
     {"digest": "9adfa7701465ad9e", "workload": "clustered_1m", "leaf_capacity": 48, "max_level": 12,
@@ -78,6 +80,8 @@ MEASURED_TRAFFIC = [
      "fetch_bytes": 40127199, "write_bytes": 290706072, "valu_insts": 162763306},
     {"digest": "9adfa7701465ad9e", "workload": "clustered_1m", "leaf_capacity": 96, "max_level": 12,
      "fetch_bytes": 37453098, "write_bytes": 290729992, "valu_insts": 174469002},
+    {"digest": "9adfa7701465ad9e", "workload": "clustered_1m", "leaf_capacity": 24, "max_level": 14,
+     "fetch_bytes": 55767587, "write_bytes": 290656272, "valu_insts": 143746888},
     {"digest": "9adfa7701465ad9e", "workload": "clustered_1m", "leaf_capacity": 32, "max_level": 14,
      "fetch_bytes": 51718662, "write_bytes": 290709408, "valu_insts": 144770354},
     {"digest": "9adfa7701465ad9e", "workload": "clustered_1m", "leaf_capacity": 48, "max_level": 14,
@@ -86,6 +90,12 @@ MEASURED_TRAFFIC = [
      "fetch_bytes": 40372394, "write_bytes": 290692296, "valu_insts": 161846035},
     {"digest": "9adfa7701465ad9e", "workload": "clustered_1m", "leaf_capacity": 96, "max_level": 14,
      "fetch_bytes": 37656760, "write_bytes": 290724896, "valu_insts": 173701547},
+    {"digest": "9adfa7701465ad9e", "workload": "clustered_1m", "leaf_capacity": 32, "max_level": 16,
+     "fetch_bytes": 51747844, "write_bytes": 290688760, "valu_insts": 144708232},
+    {"digest": "9adfa7701465ad9e", "workload": "clustered_1m", "leaf_capacity": 48, "max_level": 16,
+     "fetch_bytes": 45383506, "write_bytes": 290706072, "valu_insts": 151134466},
+    {"digest": "9adfa7701465ad9e", "workload": "clustered_1m", "leaf_capacity": 64, "max_level": 16,
+     "fetch_bytes": 40397928, "write_bytes": 290736048, "valu_insts": 161788745},
 ]
 
 
