@@ -361,7 +361,8 @@ class Context:
 
     def refit_tick(self):
         """Reuse the last full build's index with the current positions
-        (exact; node boxes grow by the objects' drift since that build)."""
+        (exact; leaf boxes are recomputed from the objects, inner node
+        boxes grow by the objects' drift since that build)."""
         self._check(lib().mknn_refit_tick(self._h))
 
     def query(self, k=None, issuers=None, ks=None, nq=None):

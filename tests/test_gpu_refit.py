@@ -1,7 +1,8 @@
 """GPU: index reuse across ticks (refit ticks).  The objects keep the last
-full build's order, leaves and node tables; queries prune with node boxes
-grown by the objects' drift, and must still return exactly the oracle's
-answer on the current positions."""
+full build's order, leaves and node tables; each leaf's box becomes the
+bounding box of its objects' current positions, queries prune inner nodes
+with boxes grown by the objects' drift, and must still return exactly the
+oracle's answer on the current positions."""
 import numpy as np
 import pytest
 
