@@ -156,7 +156,8 @@ typedef struct mknn_stats {
     int64_t wavefronts;           /* query wavefronts run */
     /* Index reuse: refit ticks since the last full build, and the largest
      * per-axis displacement of any object since that build (0 right after
-     * it), by which node boxes are grown during queries. */
+     * it), by which inner node boxes are grown during queries (leaf boxes
+     * are recomputed by each refit). */
     int64_t refits;
     float drift;
     float reserved2;
